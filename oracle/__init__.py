@@ -1,0 +1,289 @@
+"""Oracle — TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 CPU definitions of everything the GPU library computes, for SU(2)
+Wilson fermions in the fundamental and adjoint representations.  Only the
+test suite, the smoke check and the benchmark's CPU-baseline leg may import
+this package; the GPU library never does, and the two share no code.
+
+The paper (arXiv:2411.18511) reports the performance of the unimproved
+Wilson-Dirac operator (Sec. 2.1, Table 1), its even/odd preconditioned form
+used inside HMC (Sec. 2.1), fermions in the fundamental and higher
+representations (Sec. 1) and "a range of inverters" (abstract), without
+writing any of them down.  The readings taken here are standard lattice field
+theory; the C part (``oracle.c``) states the operator conventions in its
+header.  Additional readings fixed in this module:
+
+* Even/odd: parity(x) = (t + x1 + x2 + x3) mod 2, even = 0.  With m = 4 + m0,
+  D = [[m, D_eo], [D_oe, m]] in (even, odd) blocks, D_eo = -H_eo / 2, and the
+  preconditioned operator on even sites is the Schur complement
+  D^ = m - (1/m) D_eo D_oe (Sec. 2.1, "even-odd preconditioned version").
+* Daggers use gamma5-hermiticity, D^+ = g5 D g5 (g5 = g0 g1 g2 g3).
+* The solver is conjugate gradients (Hestenes-Stiefel) on A = D^+ D^ over
+  even sites, from x0 = 0, with residual ||b - A x|| / ||b|| (not squared).
+* Adjoint representation R_ab(U) = tr(s_a U s_b U^+) / 2 (real 3x3).
+* Force: G = dL/dRe U + i dL/dIm U for L = Re<X, D[U] Y>; for the real
+  adjoint links the derivative is Re G.
+* Fermion action S = phi^+ A^{-1} phi on even sites; dS/dU = (2/m) G[X, Y]
+  with xi = A^{-1} phi, eta = D^ xi, Y = (xi, D_oe xi), X = (eta, D_eo^+ eta).
+
+Field layouts are natural: gauge [4, T, L1, L2, L3, N, N], spinor
+[T, L1, L2, L3, 4, N] (spin-major, then colour).  Even-site fields are stored
+as full-lattice arrays whose odd sites are zero.
+"""
+import ctypes
+import os
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _b
+
+            _b.build()
+        lib = ctypes.CDLL(_LIBPATH)
+        P = ctypes.c_void_p
+        lib.oracle_gamma.argtypes = [ctypes.c_int, P]
+        lib.oracle_hopping.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.oracle_dirac.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double]
+        lib.oracle_represent_adjoint.argtypes = [ctypes.c_long, P, P]
+        lib.oracle_force.argtypes = [P, ctypes.c_int, P, P, P]
+        lib.oracle_plaquette.argtypes = [P, ctypes.c_int, P]
+        lib.oracle_plaquette.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims_arr(dims):
+    return np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+
+
+def _cplx(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _dims_of_spinor(psi):
+    return tuple(psi.shape[:4])
+
+
+# ---------------------------------------------------------------------------
+# Basic objects
+# ---------------------------------------------------------------------------
+
+def gamma(mu):
+    """Euclidean gamma matrix g_mu of the chiral basis (4x4 complex)."""
+    out = np.zeros((4, 4), np.complex128)
+    _load().oracle_gamma(int(mu), _ptr(out))
+    return out
+
+
+def gamma5():
+    """g5 = g0 g1 g2 g3."""
+    return gamma(0) @ gamma(1) @ gamma(2) @ gamma(3)
+
+
+def apply_gamma5(psi):
+    """Multiply every site's spinor by g5 (acts on the spin index)."""
+    return np.einsum("ab,...bi->...ai", gamma5(), psi)
+
+
+def parity(dims):
+    """Array of site parities (t + x1 + x2 + x3) mod 2, shape dims."""
+    t, x1, x2, x3 = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    return (t + x1 + x2 + x3) % 2
+
+
+def restrict(psi, par):
+    """Copy of psi with the sites of the other parity set to zero."""
+    mask = parity(_dims_of_spinor(psi)) == par
+    return psi * mask[..., None, None]
+
+
+def inner(a, b):
+    """<a, b> = sum conj(a) b."""
+    return np.vdot(a.ravel(), b.ravel())
+
+
+def norm(a):
+    return float(np.sqrt(np.real(inner(a, a))))
+
+
+def _links_complex(U):
+    return _cplx(U)
+
+
+# ---------------------------------------------------------------------------
+# Operators
+# ---------------------------------------------------------------------------
+
+def hopping(U, psi, mask=3):
+    """(H psi) on the sites whose parity bit is in mask (1 even, 2 odd, 3 all)."""
+    dims = _dims_of_spinor(psi)
+    n = psi.shape[-1]
+    psi = _cplx(psi)
+    out = np.empty_like(psi)
+    _load().oracle_hopping(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), _ptr(psi),
+                           _ptr(out), int(mask))
+    return out
+
+
+def dirac(U, psi, m0):
+    """D psi = (4 + m0) psi - H psi / 2 on the whole lattice."""
+    dims = _dims_of_spinor(psi)
+    n = psi.shape[-1]
+    psi = _cplx(psi)
+    out = np.empty_like(psi)
+    _load().oracle_dirac(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), _ptr(psi),
+                         _ptr(out), float(m0))
+    return out
+
+
+def dirac_dagger(U, psi, m0):
+    """D^+ psi = g5 D g5 psi."""
+    return apply_gamma5(dirac(U, apply_gamma5(psi), m0))
+
+
+def hop_block(U, psi, target):
+    """Off-diagonal block of D: D_eo psi_o (target=0) or D_oe psi_e (target=1).
+
+    Reads psi on the sites of parity 1 - target only; returns a field that is
+    zero off the target parity.
+    """
+    src = restrict(psi, 1 - target)
+    return -0.5 * hopping(U, src, 1 << target)
+
+
+def hop_block_dagger(U, psi, target):
+    """(D_{1-target, target})^+ psi = g5 D_{target,1-target} g5 psi."""
+    return apply_gamma5(hop_block(U, apply_gamma5(psi), target))
+
+
+def dhat(U, psi_e, m0):
+    """Even/odd preconditioned operator D^ psi_e = m psi_e - (1/m) D_eo D_oe psi_e."""
+    m = 4.0 + m0
+    psi_e = restrict(psi_e, 0)
+    t_o = hop_block(U, psi_e, 1)
+    return m * psi_e - hop_block(U, t_o, 0) / m
+
+
+def dhat_dagger(U, psi_e, m0):
+    return apply_gamma5(dhat(U, apply_gamma5(psi_e), m0))
+
+
+def normal_op(U, x_e, m0):
+    """A x = D^+ D^ x on even sites."""
+    return dhat_dagger(U, dhat(U, x_e, m0), m0)
+
+
+def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None):
+    """Conjugate gradients for (D^+ D^) x = b on even sites.
+
+    Plain Hestenes-Stiefel iteration; stops when the recursively updated
+    residual satisfies ||r|| <= tol ||b||, then recomputes the true residual
+    b - A x and continues from it if that check fails.  Returns (x, info).
+    """
+    b_e = restrict(_cplx(b_e), 0)
+    bnorm = norm(b_e)
+    x = np.zeros_like(b_e) if x0 is None else restrict(_cplx(x0), 0)
+    r = b_e - normal_op(U, x, m0) if x0 is not None else b_e.copy()
+    p = r.copy()
+    rr = np.real(inner(r, r))
+    iters = 0
+    t0 = time.perf_counter()
+    while iters < maxiter:
+        if np.sqrt(rr) <= tol * bnorm:
+            r_true = b_e - normal_op(U, x, m0)
+            rr_true = np.real(inner(r_true, r_true))
+            if np.sqrt(rr_true) <= tol * bnorm:
+                break
+            r = r_true
+            p = r.copy()
+            rr = rr_true
+        Ap = normal_op(U, p, m0)
+        alpha = rr / np.real(inner(p, Ap))
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rr_new = np.real(inner(r, r))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        iters += 1
+    res = norm(b_e - normal_op(U, x, m0)) / bnorm
+    return x, {"iters": iters, "true_rel_residual": res, "seconds": time.perf_counter() - t0}
+
+
+def true_residual(U, b_e, x_e, m0):
+    """||b - D^+ D^ x|| / ||b|| on even sites."""
+    b_e = restrict(_cplx(b_e), 0)
+    return norm(b_e - normal_op(U, restrict(_cplx(x_e), 0), m0)) / norm(b_e)
+
+
+# ---------------------------------------------------------------------------
+# Gauge-field maps
+# ---------------------------------------------------------------------------
+
+def represent_adjoint(Uf):
+    """R_ab(U) = tr(s_a U s_b U^+) / 2 for every link; real, shape [..., 3, 3]."""
+    Uf = _cplx(Uf)
+    shape = Uf.shape[:-2]
+    nl = int(np.prod(shape))
+    R = np.empty(shape + (3, 3), np.float64)
+    _load().oracle_represent_adjoint(nl, _ptr(Uf), _ptr(R))
+    return R
+
+
+def plaquette(U):
+    """Average plaquette (1/N) Re tr of the elementary loop, over sites and planes."""
+    n = U.shape[-1]
+    dims = U.shape[1:5]
+    return _load().oracle_plaquette(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)))
+
+
+# ---------------------------------------------------------------------------
+# Derivatives
+# ---------------------------------------------------------------------------
+
+def force(X, Y, real_links=False):
+    """G = dL/dRe U + i dL/dIm U for L = Re<X, D[U] Y>; shape [4, T, L1, L2, L3, N, N].
+
+    For real (adjoint) links the derivative with respect to the real entries
+    is Re G, returned when real_links is true.
+    """
+    dims = _dims_of_spinor(X)
+    n = X.shape[-1]
+    X = _cplx(X)
+    Y = _cplx(Y)
+    G = np.empty((4,) + tuple(dims) + (n, n), np.complex128)
+    _load().oracle_force(_ptr(_dims_arr(dims)), n, _ptr(X), _ptr(Y), _ptr(G))
+    return G.real.copy() if real_links else G
+
+
+def action_force_fields(U, xi_e, m0):
+    """The (X, Y) pair whose force gives dS/dU = (2/m) G[X, Y] for S = phi^+ A^{-1} phi.
+
+    xi_e = A^{-1} phi; eta = D^ xi; Y = (xi on even, D_oe xi on odd);
+    X = (eta on even, D_eo^+ eta on odd).
+    """
+    xi_e = restrict(_cplx(xi_e), 0)
+    eta = dhat(U, xi_e, m0)
+    Y = xi_e + hop_block(U, xi_e, 1)
+    X = eta + hop_block_dagger(U, eta, 1)
+    return X, Y
+
+
+def action_force(U, phi_e, m0, tol=1e-12, maxiter=10000, real_links=False):
+    """dS/dU for S = Re<phi, A^{-1} phi>, A = D^+ D^ (solve by cg)."""
+    xi, info = cg(U, phi_e, m0, tol=tol, maxiter=maxiter)
+    X, Y = action_force_fields(U, xi, m0)
+    m = 4.0 + m0
+    return (2.0 / m) * force(X, Y, real_links=real_links), xi, info

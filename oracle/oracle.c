@@ -1,0 +1,290 @@
+/*
+ * Oracle — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 CPU evaluation of the Wilson-Dirac
+ * hopping term, the adjoint-representation map, the derivative of
+ * Re<X, D[U] Y> with respect to the links, and the plaquette, for SU(2)
+ * gauge fields.  It exists to check the GPU library; only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code with the GPU library.
+ *
+ * The paper (arXiv:2411.18511, "Scaling SU(2) to 1000 GPUs using HiRep",
+ * Sec. 2.1 and Table 1) names the unimproved Wilson-Dirac operator with
+ * SU(2) links in the fundamental and in higher representations, but never
+ * writes it down.  The definitions used here are the textbook ones, fixed as
+ * follows (every choice is a reading of a silent paper):
+ *
+ *   Lattice  x = (t, x1, x2, x3), extents (T, L1, L2, L3); mu = 0 is time.
+ *            lex(x) = ((t*L1 + x1)*L2 + x2)*L3 + x3.
+ *   Fields   U[mu][lex][i][j]  (N x N complex, N = 2 fund, 3 adjoint with
+ *            zero imaginary part), psi[lex][spin][colour] (4 x N complex).
+ *   Gammas   chiral basis, 2x2 blocks: g0 = [[0,1],[1,0]],
+ *            gk = [[0,-i s_k],[i s_k,0]] with Pauli matrices s_k.
+ *   Boundary periodic in space, antiperiodic in time, carried by the hop
+ *            sign s_mu(x) = -1 iff mu = 0 and t(x) = T-1 (links stay periodic).
+ *   Hopping  (H psi)(x) = sum_mu [ s_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
+ *                               + s_mu(x-mu) (1 + g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *   Operator D = (4 + m0) - H/2.
+ *
+ * Every function below evaluates those sums literally, with full 4x4 gamma
+ * matrices and no spin-projection shortcut.
+ */
+#include <complex.h>
+#include <math.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define MAXN 3
+
+/* Coordinates of lexicographic site index s. */
+static void coords(const int *d, long s, int x[4])
+{
+    x[3] = (int)(s % d[3]); s /= d[3];
+    x[2] = (int)(s % d[2]); s /= d[2];
+    x[1] = (int)(s % d[1]); s /= d[1];
+    x[0] = (int)s;
+}
+
+static long lexidx(const int *d, const int x[4])
+{
+    return (((long)x[0] * d[1] + x[1]) * d[2] + x[2]) * d[3] + x[3];
+}
+
+static long volume(const int *d) { return (long)d[0] * d[1] * d[2] * d[3]; }
+
+/* The four Euclidean gamma matrices of the chiral basis (see header). */
+static void gamma_matrix(int mu, cplx g[4][4])
+{
+    /* Pauli matrices s1, s2, s3 */
+    const cplx pauli[3][2][2] = {
+        {{0, 1}, {1, 0}},
+        {{0, -I}, {I, 0}},
+        {{1, 0}, {0, -1}},
+    };
+    memset(g, 0, sizeof(cplx) * 16);
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            if (mu == 0) {
+                g[a][2 + b] = (a == b) ? 1 : 0;
+                g[2 + a][b] = (a == b) ? 1 : 0;
+            } else {
+                g[a][2 + b] = -I * pauli[mu - 1][a][b];
+                g[2 + a][b] = I * pauli[mu - 1][a][b];
+            }
+        }
+}
+
+/* Exported so the tests can check the Clifford algebra of the basis used. */
+void oracle_gamma(int mu, cplx *out)
+{
+    cplx g[4][4];
+    gamma_matrix(mu, g);
+    memcpy(out, g, sizeof(g));
+}
+
+/* Hop sign s_mu(x) for the time-antiperiodic boundary. */
+static double hop_sign(const int *d, int mu, const int x[4])
+{
+    return (mu == 0 && x[0] == d[0] - 1) ? -1.0 : 1.0;
+}
+
+/*
+ * out(x) = (H psi)(x) on the sites whose parity bit is set in `mask`
+ * (bit 0: even sites, bit 1: odd sites); every other site of `out` is set
+ * to zero.  Parity of x is (t + x1 + x2 + x3) mod 2.
+ */
+void oracle_hopping(const int *d, int n, const cplx *U, const cplx *psi,
+                    cplx *out, int mask)
+{
+    const long V = volume(d);
+    cplx G[4][4][4];
+    for (int mu = 0; mu < 4; mu++) gamma_matrix(mu, G[mu]);
+
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        int x[4];
+        coords(d, s, x);
+        const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+        cplx acc[4][MAXN];
+        memset(acc, 0, sizeof(acc));
+        if (mask & (1 << par)) {
+            for (int mu = 0; mu < 4; mu++) {
+                int y[4];
+                cplx v[4][MAXN];
+
+                /* forward term: s_mu(x) (1 - g_mu) U_mu(x) psi(x + mu) */
+                memcpy(y, x, sizeof(y));
+                y[mu] = (x[mu] + 1) % d[mu];
+                const long sf = lexidx(d, y);
+                const double sgf = hop_sign(d, mu, x);
+                const cplx *Uf = U + ((long)mu * V + s) * n * n;
+                for (int a = 0; a < 4; a++)
+                    for (int i = 0; i < n; i++) {
+                        cplx z = 0;
+                        for (int j = 0; j < n; j++)
+                            z += Uf[i * n + j] * psi[(sf * 4 + a) * n + j];
+                        v[a][i] = z;
+                    }
+                for (int a = 0; a < 4; a++)
+                    for (int i = 0; i < n; i++) {
+                        cplx z = v[a][i];
+                        for (int b = 0; b < 4; b++) z -= G[mu][a][b] * v[b][i];
+                        acc[a][i] += sgf * z;
+                    }
+
+                /* backward term: s_mu(x-mu) (1 + g_mu) U_mu(x-mu)^+ psi(x - mu) */
+                memcpy(y, x, sizeof(y));
+                y[mu] = (x[mu] - 1 + d[mu]) % d[mu];
+                const long sb = lexidx(d, y);
+                const double sgb = hop_sign(d, mu, y);
+                const cplx *Ub = U + ((long)mu * V + sb) * n * n;
+                for (int a = 0; a < 4; a++)
+                    for (int i = 0; i < n; i++) {
+                        cplx z = 0;
+                        for (int j = 0; j < n; j++)
+                            z += conj(Ub[j * n + i]) * psi[(sb * 4 + a) * n + j];
+                        v[a][i] = z;
+                    }
+                for (int a = 0; a < 4; a++)
+                    for (int i = 0; i < n; i++) {
+                        cplx z = v[a][i];
+                        for (int b = 0; b < 4; b++) z += G[mu][a][b] * v[b][i];
+                        acc[a][i] += sgb * z;
+                    }
+            }
+        }
+        for (int a = 0; a < 4; a++)
+            for (int i = 0; i < n; i++) out[(s * 4 + a) * n + i] = acc[a][i];
+    }
+}
+
+/* out = (4 + m0) psi - H psi / 2 on all sites. */
+void oracle_dirac(const int *d, int n, const cplx *U, const cplx *psi,
+                  cplx *out, double m0)
+{
+    const long V = volume(d);
+    oracle_hopping(d, n, U, psi, out, 3);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < V * 4 * n; k++)
+        out[k] = (4.0 + m0) * psi[k] - 0.5 * out[k];
+}
+
+/*
+ * Adjoint representation of SU(2): R_ab(U) = (1/2) tr(s_a U s_b U^+),
+ * a, b = 1..3, a real 3x3 matrix.  Uf is [nlinks][2][2], R is [nlinks][3][3].
+ */
+void oracle_represent_adjoint(long nlinks, const cplx *Uf, double *R)
+{
+    const cplx pauli[3][2][2] = {
+        {{0, 1}, {1, 0}},
+        {{0, -I}, {I, 0}},
+        {{1, 0}, {0, -1}},
+    };
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < nlinks; l++) {
+        const cplx *u = Uf + l * 4;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                /* tr(s_a U s_b U^+) = sum_{ijkm} s_a[i][j] U[j][k] s_b[k][m] conj(U[i][m]) */
+                cplx tr = 0;
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 2; j++)
+                        for (int k = 0; k < 2; k++)
+                            for (int m = 0; m < 2; m++)
+                                tr += pauli[a][i][j] * u[j * 2 + k] * pauli[b][k][m] *
+                                      conj(u[i * 2 + m]);
+                R[l * 9 + a * 3 + b] = 0.5 * creal(tr);
+            }
+    }
+}
+
+/*
+ * Derivative of L = Re<X, D[U] Y> with respect to the links, in the
+ * convention G = dL/dRe(U) + i dL/dIm(U) for each entry of U_mu(x).
+ * D depends on U only through the hopping term, linearly, so G depends on
+ * X and Y alone:
+ *   G_mu(x)_ij = -1/2 s_mu(x) sum_spin [ X(x)_{s,i} conj(((1 - g_mu) Y(x+mu))_{s,j})
+ *                                      + ((1 + g_mu) Y(x))_{s,i} conj(X(x+mu)_{s,j}) ]
+ * (the first sum comes from the forward term at x, the second from the
+ * backward term at x + mu, which also uses U_mu(x)).  G is [mu][lex][i][j].
+ */
+void oracle_force(const int *d, int n, const cplx *X, const cplx *Y, cplx *Gout)
+{
+    const long V = volume(d);
+    cplx G[4][4][4];
+    for (int mu = 0; mu < 4; mu++) gamma_matrix(mu, G[mu]);
+
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        int x[4];
+        coords(d, s, x);
+        for (int mu = 0; mu < 4; mu++) {
+            int y[4];
+            memcpy(y, x, sizeof(y));
+            y[mu] = (x[mu] + 1) % d[mu];
+            const long sf = lexidx(d, y);
+            const double sg = hop_sign(d, mu, x);
+            cplx pm[4][MAXN], pp[4][MAXN];
+            /* pm = (1 - g_mu) Y(x+mu),  pp = (1 + g_mu) Y(x) */
+            for (int a = 0; a < 4; a++)
+                for (int i = 0; i < n; i++) {
+                    cplx zm = Y[(sf * 4 + a) * n + i];
+                    cplx zp = Y[(s * 4 + a) * n + i];
+                    for (int b = 0; b < 4; b++) {
+                        zm -= G[mu][a][b] * Y[(sf * 4 + b) * n + i];
+                        zp += G[mu][a][b] * Y[(s * 4 + b) * n + i];
+                    }
+                    pm[a][i] = zm;
+                    pp[a][i] = zp;
+                }
+            cplx *g = Gout + ((long)mu * V + s) * n * n;
+            for (int i = 0; i < n; i++)
+                for (int j = 0; j < n; j++) {
+                    cplx z = 0;
+                    for (int a = 0; a < 4; a++)
+                        z += X[(s * 4 + a) * n + i] * conj(pm[a][j]) +
+                             pp[a][i] * conj(X[(sf * 4 + a) * n + j]);
+                    g[i * n + j] = -0.5 * sg * z;
+                }
+        }
+    }
+}
+
+/*
+ * Average plaquette (1/N) Re tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+ * over all sites and the six planes mu < nu.
+ */
+double oracle_plaquette(const int *d, int n, const cplx *U)
+{
+    const long V = volume(d);
+    double total = 0;
+#pragma omp parallel for reduction(+ : total) schedule(static)
+    for (long s = 0; s < V; s++) {
+        int x[4];
+        coords(d, s, x);
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++) {
+                int y[4];
+                memcpy(y, x, sizeof(y));
+                y[mu] = (x[mu] + 1) % d[mu];
+                const long sxm = lexidx(d, y);
+                memcpy(y, x, sizeof(y));
+                y[nu] = (x[nu] + 1) % d[nu];
+                const long sxn = lexidx(d, y);
+                const cplx *A = U + ((long)mu * V + s) * n * n;
+                const cplx *B = U + ((long)nu * V + sxm) * n * n;
+                const cplx *C = U + ((long)mu * V + sxn) * n * n;
+                const cplx *E = U + ((long)nu * V + s) * n * n;
+                cplx tr = 0;
+                for (int i = 0; i < n; i++)
+                    for (int j = 0; j < n; j++)
+                        for (int k = 0; k < n; k++)
+                            for (int l = 0; l < n; l++)
+                                tr += A[i * n + j] * B[j * n + k] * conj(C[l * n + k]) *
+                                      conj(E[i * n + l]);
+                total += creal(tr) / n;
+            }
+    }
+    return total / (6.0 * V);
+}

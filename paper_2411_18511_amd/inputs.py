@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs: SU(2) gauge fields and Gaussian spinor fields.
+
+This module holds no part of the Dirac operator, the solver or the force; it
+only draws random fields, in the natural layout
+
+* gauge links  ``U[mu, t, x1, x2, x3, i, j]`` complex128 (fundamental SU(2)),
+* spinors      ``psi[t, x1, x2, x3, spin, colour]`` complex128,
+
+with numpy's PCG64 generator.  Both the GPU library's tests and the CPU
+oracle consume the same arrays.
+
+The paper timed its operator on gauge fields it does not describe (Sec. 3,
+Table 1); bandwidth does not depend on field content, so these stand in:
+
+* Haar-random links: a = g / |g| with g ~ N(0, 1)^4 and
+  U = a0 + i (a1 s1 + a2 s2 + a3 s3)  (uniform on SU(2) = S^3).
+* "Heat-bath-like" links: a = (1, eps g1, eps g2, eps g3) / norm, i.e. Haar
+  directions pulled toward the identity.  For independent links the mean
+  plaquette is E[a0]^4, so eps is chosen by bisection to make E[a0]^4 equal
+  the requested plaquette (0.6 by default).
+* Spinors: real and imaginary parts i.i.d. N(0, 1/2).
+"""
+import numpy as np
+
+
+def rng_for(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _su2_from_quaternion(a):
+    """U = a0 + i a.s for unit 4-vectors a (last axis); returns [..., 2, 2]."""
+    a0, a1, a2, a3 = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    U = np.empty(a.shape[:-1] + (2, 2), np.complex128)
+    U[..., 0, 0] = a0 + 1j * a3
+    U[..., 0, 1] = a2 + 1j * a1
+    U[..., 1, 0] = -a2 + 1j * a1
+    U[..., 1, 1] = a0 - 1j * a3
+    return U
+
+
+def haar_su2(rng, shape):
+    g = rng.standard_normal(tuple(shape) + (4,))
+    g /= np.linalg.norm(g, axis=-1, keepdims=True)
+    return _su2_from_quaternion(g)
+
+
+def _mean_a0(eps):
+    """E[1 / sqrt(1 + eps^2 r^2)] for r ~ chi(3), by quadrature on a fine grid."""
+    r = np.linspace(0.0, 12.0, 200001)
+    w = np.sqrt(2.0 / np.pi) * r * r * np.exp(-0.5 * r * r)
+    f = w / np.sqrt(1.0 + (eps * r) ** 2)
+    return float(np.trapezoid(f, r) / np.trapezoid(w, r))
+
+
+def smearing_for_plaquette(target=0.6):
+    """eps such that E[a0]^4 == target for the heat-bath-like generator."""
+    lo, hi = 0.0, 50.0
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        if _mean_a0(mid) ** 4 > target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def smeared_su2(rng, shape, eps):
+    g = rng.standard_normal(tuple(shape) + (3,))
+    a = np.concatenate([np.ones(tuple(shape) + (1,)), eps * g], axis=-1)
+    a /= np.linalg.norm(a, axis=-1, keepdims=True)
+    return _su2_from_quaternion(a)
+
+
+def gauge_field(dims, seed, kind="haar", plaquette=0.6):
+    """Fundamental SU(2) gauge field [4, T, L1, L2, L3, 2, 2] (complex128)."""
+    rng = rng_for(seed)
+    shape = (4,) + tuple(int(d) for d in dims)
+    if kind == "haar":
+        return haar_su2(rng, shape)
+    if kind == "smeared":
+        return smeared_su2(rng, shape, smearing_for_plaquette(plaquette))
+    if kind == "unit":
+        U = np.zeros(shape + (2, 2), np.complex128)
+        U[..., 0, 0] = 1
+        U[..., 1, 1] = 1
+        return U
+    raise ValueError(f"unknown gauge kind {kind!r}")
+
+
+def gaussian_spinor(dims, ncolour, seed, nrhs=None):
+    """Gaussian spinor field [T, L1, L2, L3, 4, N] (or [nrhs, ...]), complex128."""
+    rng = rng_for(seed)
+    shape = tuple(int(d) for d in dims) + (4, int(ncolour))
+    if nrhs is not None:
+        shape = (int(nrhs),) + shape
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (re + 1j * im) * np.sqrt(0.5)
+
+
+def gauge_transform(rng, dims):
+    """Random site-local SU(2) matrices g(x), shape [T, L1, L2, L3, 2, 2]."""
+    return haar_su2(rng, tuple(int(d) for d in dims))
