@@ -1,0 +1,367 @@
+/*
+ * hrd.h — C ABI of libhrd, an MI355X (gfx950) library for the Wilson-Dirac
+ * operator of SU(2) lattice gauge theory with fermions in the fundamental or
+ * adjoint representation, its even/odd preconditioned form, conjugate-gradient
+ * solvers on D^+D^ (FP64 and mixed precision), the fermion force, and batched
+ * multi-right-hand-side / mixed-volume variants.
+ *
+ * Paper: arXiv:2411.18511, "Scaling SU(2) to 1000 GPUs using HiRep".  The
+ * paper benchmarks the unimproved Wilson-Dirac operator (Sec. 2.1, Table 1),
+ * uses its even/odd preconditioned version inside HMC (Sec. 2.1), runs
+ * fermions in higher representations (Sec. 1) and mentions a range of
+ * inverters (abstract); it writes none of them down.  The definitions below
+ * are the standard ones this library implements.
+ *
+ * ---------------------------------------------------------------------------
+ * CONVENTIONS
+ *   Lattice   x = (t, x1, x2, x3), extents dims = {T, L1, L2, L3}, each even
+ *             and >= 2; mu = 0 is time.  V = T L1 L2 L3, Vh = V / 2.
+ *   Boundary  periodic in space, antiperiodic in time, applied as the hop sign
+ *             s_mu(x) = -1 iff mu = 0 and t(x) = T - 1; the links themselves
+ *             stay periodic.
+ *   Gammas    chiral basis in 2x2 blocks: g0 = [[0, 1], [1, 0]],
+ *             gk = [[0, -i sk], [i sk, 0]] (sk Pauli matrices);
+ *             g5 = g0 g1 g2 g3 = diag(-1, -1, +1, +1).
+ *   Hopping   (H psi)(x) = sum_mu [ s_mu(x) (1 - g_mu) U_mu(x) psi(x + mu)
+ *                                 + s_mu(x - mu) (1 + g_mu) U_mu(x - mu)^+ psi(x - mu) ]
+ *   Operator  D = m - H / 2 with m = 4 + m0 (bare mass m0).
+ *   Even/odd  parity(x) = (t + x1 + x2 + x3) mod 2, even = 0.  In (even, odd)
+ *             blocks D = [[m, D_eo], [D_oe, m]] with D_eo = -H_eo / 2, and the
+ *             preconditioned operator on even sites is the Schur complement
+ *             D^ = m - (1/m) D_eo D_oe.  D^+ = g5 D^ g5.
+ *   Reps      FUND: U in SU(2), 2 colours.  ADJ: R_ab(U) = tr(s_a U s_b U^+)/2,
+ *             a real orthogonal 3x3 matrix, 3 colours.
+ *
+ * SITE ORDER (both parities)
+ *   lex(x) = ((t L1 + x1) L2 + x2) L3 + x3.  A site of parity p has index
+ *   lex(x) >> 1 within the parity-p block (a bijection since L3 is even).
+ *
+ * PACKED LAYOUTS ("library layout"; all device memory)
+ *   A field of one parity is a sequence of PLANES; a plane is an array of Vh
+ *   elements, one per site, in site order.  Spinor components are numbered
+ *   k = spin * N + colour (N = 2 FUND, 3 ADJ; 4N components).
+ *     spinor, F64 : 4N planes of complex128 (16 B): plane k = component k.
+ *     spinor, F32 : 2N planes of 2 x complex64 (16 B): plane k = components
+ *                   (2k, 2k+1).
+ *     link FUND F64: 4 planes of complex128, entries U00, U01, U10, U11.
+ *     link FUND F32: 2 planes of 2 x complex64: (U00, U01), (U10, U11).
+ *     link ADJ  F64: 4 planes of 2 x float64 holding entries (0,1) (2,3) (4,5)
+ *                    (6,7), then 1 plane of float64 holding entry 8; entry
+ *                    e = 3 a + b of R_ab.
+ *     link ADJ  F32: 2 planes of 4 x float32 (entries 0-3, 4-7), then 1 plane
+ *                    of float32 (entry 8).
+ *   A full-lattice spinor is [parity][planes][Vh], even block first.  A
+ *   gauge field is [parity][mu][planes][Vh]: block (p, mu) holds the links
+ *   U_mu(x) of the sites x of parity p.
+ *
+ * NATURAL LAYOUTS (device memory; used only by the pack/unpack calls)
+ *   spinor : complex128 [V][4][N]          (site lex, spin, colour)
+ *   gauge  : complex128 [4][V][2][2] FUND, float64 [4][V][3][3] ADJ
+ *
+ * OWNERSHIP AND ERRORS
+ *   Every field pointer is a device pointer owned by the caller; the library
+ *   never allocates device memory: temporaries come from caller-provided
+ *   workspaces whose sizes the *_bytes queries return.  Calls are enqueued on
+ *   the given stream (a hipStream_t; NULL means the null stream) and return
+ *   without synchronising unless stated.  No call aborts or throws: each
+ *   returns an hrd_status, and hrd_last_error() gives a thread-local message
+ *   for the last failure.  Output buffers must not overlap input buffers
+ *   (HRD_EALIAS).  Stream-ordered calls report launch failures (HRD_EHIP);
+ *   faults inside a kernel surface at the next synchronisation.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef HRD_H
+#define HRD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRD_OK = 0,
+    HRD_EINVAL = 1,      /* bad enum value, NULL pointer, non-finite scalar     */
+    HRD_ESHAPE = 2,      /* lattice extent odd, < 2, or too large              */
+    HRD_EALIAS = 3,      /* an output buffer overlaps an input buffer          */
+    HRD_EHIP = 4,        /* a HIP runtime call or kernel launch failed         */
+    HRD_ENOCONV = 5,     /* solver hit maxiter before reaching the tolerance   */
+    HRD_EBREAKDOWN = 6,  /* solver breakdown: <p, A p> <= 0 or NaN residual    */
+    HRD_ESIZE = 7        /* caller-provided workspace too small                */
+} hrd_status;
+
+typedef enum { HRD_FUND = 0, HRD_ADJ = 1 } hrd_rep;
+typedef enum { HRD_F64 = 0, HRD_F32 = 1 } hrd_prec;
+
+/* Which block of D a call applies (Sec. 2.1: the plain operator and the
+   even/odd preconditioned version). */
+typedef enum {
+    HRD_FULL = 0,   /* out = D psi on all V sites (full-lattice fields)          */
+    HRD_EO = 1,     /* out_e = D^ psi_e (even half fields)                       */
+    HRD_HOP_EO = 2, /* out_e = D_eo psi_o  (psi: odd half, out: even half)      */
+    HRD_HOP_OE = 3  /* out_o = D_oe psi_e  (psi: even half, out: odd half)      */
+} hrd_parity;
+
+/* Which sites a natural-layout spinor transfer covers. */
+typedef enum { HRD_SITES_ALL = 0, HRD_SITES_EVEN = 1, HRD_SITES_ODD = 2 } hrd_sites;
+
+typedef enum { HRD_CG_F64 = 0, HRD_CG_MIXED = 1 } hrd_cg_mode;
+
+typedef struct {
+    int dims[4]; /* {T, L1, L2, L3} */
+} hrd_lattice;
+
+typedef struct {
+    int iters;                    /* CG iterations (operator applications / 2)      */
+    int reliable_updates;         /* FP64 residual recomputations (mixed mode)      */
+    int restarts;                 /* true-residual checks that failed and restarted */
+    double true_rel_residual;     /* ||b - A x|| / ||b||, recomputed in FP64        */
+    double iterated_rel_residual; /* the recursively updated residual at exit       */
+    double seconds;               /* host wall time of the solve                   */
+} hrd_cg_info;
+
+/* Thread-local description of the last failure ("" if none). */
+const char *hrd_last_error(void);
+/* Library version string. */
+const char *hrd_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Sizes                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of a packed spinor on one parity (nparity = 1) or the whole lattice
+   (nparity = 2).  Returns 0 for invalid arguments. */
+size_t hrd_spinor_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity);
+
+/* Bytes of a packed gauge field (all 4 V links). */
+size_t hrd_gauge_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec);
+
+/* ------------------------------------------------------------------------ */
+/* Gauge preparation — links are prepared once per gauge field, as the paper
+   does for its derived fields whenever the gauge field changes (Sec. 2.2).  */
+/* ------------------------------------------------------------------------ */
+
+/* Natural -> packed gauge field.  U_nat is complex128 [4][V][2][2] for FUND
+   and float64 [4][V][3][3] for ADJ; U receives hrd_gauge_bytes(lat, rep, prec)
+   bytes (FP32 output is rounded to nearest). */
+hrd_status hrd_pack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                          const void *U_nat, void *U, void *stream);
+
+/* Packed -> natural gauge field (also used for force fields, which share the
+   gauge layout).  Output dtype as for hrd_pack_gauge, always FP64. */
+hrd_status hrd_unpack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                            const void *U, void *U_nat, void *stream);
+
+/* Adjoint representation of a packed FP64 fundamental field (Sec. 1, higher
+   representations): U_adj(x, mu) = R(U_fund(x, mu)), R_ab = tr(s_a U s_b U^+)/2,
+   written in the packed ADJ layout of precision prec_out. */
+hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj,
+                         hrd_prec prec_out, void *stream);
+
+/* Chain rule through the adjoint map: given the packed FP64 fundamental field
+   U_fund and a packed FP64 ADJ field g = dL/dR (real), writes the packed FP64
+   FUND field G_fund = dL/dRe U + i dL/dIm U = sum_ab g_ab s_a U s_b. */
+hrd_status hrd_represent_backward(const hrd_lattice *lat, const void *U_fund,
+                                  const void *g_adj, void *G_fund, void *stream);
+
+/* Packed FP64 -> packed FP32 gauge field (round to nearest). */
+hrd_status hrd_convert_gauge(const hrd_lattice *lat, hrd_rep rep, const void *U64,
+                             void *U32, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Spinor transfers                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Natural complex128 [V][4][N] -> packed.  sites = ALL writes a full-lattice
+   packed field; EVEN / ODD write a one-parity packed field from the sites of
+   that parity (the other sites of psi_nat are not read). */
+hrd_status hrd_pack_spinor(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                           hrd_sites sites, const void *psi_nat, void *psi,
+                           void *stream);
+
+/* Packed -> natural complex128 [V][4][N].  For EVEN / ODD only the sites of
+   that parity are written; the others are left untouched. */
+hrd_status hrd_unpack_spinor(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                             hrd_sites sites, const void *psi, void *psi_nat,
+                             void *stream);
+
+/* Precision conversion of nparity (1 or 2) parities of packed spinor:
+   to_f32 != 0: F64 -> F32 (round to nearest); else F32 -> F64 (exact). */
+hrd_status hrd_convert_spinor(const hrd_lattice *lat, hrd_rep rep, int nparity,
+                              int to_f32, const void *in, void *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* The operator (Sec. 2.1: unimproved Wilson-Dirac operator and its even/odd
+   preconditioned version).                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes hrd_dirac_apply needs: one odd half field for HRD_EO, 0
+   otherwise. */
+size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                                 hrd_parity parity);
+
+/* out = X psi with X = D, D^, D_eo or D_oe as selected by `parity`; with
+   dagger != 0, X is replaced by g5 X g5 (= X^+ for FULL and EO; for
+   HOP_EO it is (D_oe)^+, for HOP_OE it is (D_eo)^+).  U is the packed gauge
+   field of (rep, prec); psi and out are packed spinors of the sizes the
+   parity mode implies; work holds hrd_dirac_workspace_bytes bytes (may be
+   NULL when that is 0).  Asynchronous. */
+hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                           const void *U, const void *psi, void *out, double m0,
+                           hrd_parity parity, int dagger, void *work, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Level-1 linear algebra on packed spinors (the building blocks of the
+   inverters, abstract).  n_parity = 1 or 2 selects half or full fields.
+   Reductions accumulate in FP64 with a fixed-order two-stage tree, so results
+   are bitwise reproducible; they synchronise the stream and return on the
+   host.  `work` holds hrd_blas_workspace_bytes() bytes.                     */
+/* ------------------------------------------------------------------------ */
+
+size_t hrd_blas_workspace_bytes(void);
+
+/* result[0] + i result[1] = <a, b> = sum conj(a) b. */
+hrd_status hrd_blas_dot(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity,
+                        const void *a, const void *b, double *result, void *work,
+                        void *stream);
+
+/* *result = ||a||^2. */
+hrd_status hrd_blas_norm2(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity,
+                          const void *a, double *result, void *work, void *stream);
+
+/* y <- y + (a_re + i a_im) x; if result != NULL also returns ||y||^2 (fused,
+   synchronising); otherwise asynchronous. */
+hrd_status hrd_blas_axpy(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity,
+                         double a_re, double a_im, const void *x, void *y,
+                         double *result, void *work, void *stream);
+
+/* y <- x + (a_re + i a_im) y.  Asynchronous. */
+hrd_status hrd_blas_xpay(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity,
+                         const void *x, double a_re, double a_im, void *y, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Conjugate gradients on A = D^+ D^ over even sites (abstract: inverters;
+   Sec. 2.1: the even/odd operator used in the HMC).                         */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes for hrd_cg_solve in the given mode. */
+size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode);
+
+/* Solves A x = b.  b and x are packed FP64 even half fields; x holds the
+   initial guess on entry (zero it for x0 = 0) and the solution on exit.
+   U64 is the packed FP64 gauge field; U32 its packed FP32 copy (required for
+   HRD_CG_MIXED, ignored for HRD_CG_F64).  Stops when the true relative
+   residual ||b - A x|| / ||b||, recomputed in FP64, is <= tol.
+     HRD_CG_F64   : every vector and reduction in FP64.
+     HRD_CG_MIXED : iterations in FP32 (operator, r, p, A p), FP64 solution
+                    accumulation and reductions, and a reliable update (FP64
+                    recomputation of the residual) whenever the iterated
+                    residual drops below delta times its largest value since
+                    the last update (delta <= 0 selects 0.1).
+   maxiter bounds the iterations.  info (may be NULL) is filled in every case.
+   Synchronises the stream.  Returns HRD_ENOCONV if the tolerance is not
+   reached, HRD_EBREAKDOWN on <p, A p> <= 0 or a non-finite residual. */
+hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
+                        const void *U64, const void *U32, const void *b, void *x,
+                        double m0, double tol, int maxiter, double delta,
+                        void *work, size_t work_bytes, hrd_cg_info *info, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Fermion force for the HMC (Sec. 2.1 mentions the HMC the even/odd operator
+   serves).                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* F = scale * dL/dU for L = Re<X, D[U] Y>, in the convention
+   dL/dU = dL/dRe U + i dL/dIm U per link entry:
+     G_mu(x) = -1/2 s_mu(x) sum_spin [ X(x) (x) ((1 - g_mu) Y(x+mu))^*
+                                     + ((1 + g_mu) Y(x)) (x) X(x+mu)^* ],
+   (a (x) b^*)_ij = a_i conj(b_j).  X and Y are packed full-lattice FP64
+   spinors; F is a packed FP64 gauge-layout field.  For ADJ the links are
+   real and F = scale * Re G.  D is linear in U, so G does not depend on U;
+   U is accepted so the call mirrors the operator's arguments and may be NULL.
+   Asynchronous. */
+hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                           const void *U, const void *X, const void *Y, void *F,
+                           double scale, void *stream);
+
+/* Workspace bytes for hrd_action_force (two full-lattice FP64 fields). */
+size_t hrd_action_force_workspace_bytes(const hrd_lattice *lat, hrd_rep rep);
+
+/* Force of the fermion action S = phi^+ (D^+ D^)^{-1} phi given the solution
+   xi = (D^+ D^)^{-1} phi (packed FP64 even half field):
+     F = scale * (2/m) G[X, Y],  eta = D^ xi,  Y = (xi, D_oe xi),
+     X = (eta, (D_eo)^+ eta),  m = 4 + m0,
+   which is scale * dS/dU.  U is the packed FP64 gauge field.  Asynchronous. */
+hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U,
+                            const void *xi, void *F, double m0, double scale,
+                            void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched multi-RHS / mixed-volume execution.  The paper advises local
+   volumes of at least 16^4 for SU(2) (Sec. 3); many small problems and many
+   right-hand sides are gathered into single persistent launches that read
+   each link once per site for all right-hand sides of a problem.            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    hrd_lattice lat;
+    hrd_rep rep;
+    int nrhs;          /* right-hand sides on this lattice (1..64)               */
+    double m0;
+    const void *U32;   /* packed FP32 gauge field                                */
+    const void *U64;   /* packed FP64 gauge field (batched CG only; else NULL)   */
+    const void *src;   /* nrhs consecutive packed half fields (see the calls)    */
+    void *dst;         /* nrhs consecutive packed half fields                    */
+} hrd_problem;
+
+/* Launch shape of the batched kernels: sites per tile (a multiple of 64),
+   right-hand sides processed per tile, threads per workgroup, and
+   workgroups per CU of the persistent grid.  Zero fields select defaults. */
+typedef struct {
+    int sites_per_tile;
+    int rhs_per_tile;
+    int block_threads;
+    int blocks_per_cu;
+} hrd_tune;
+
+/* Workspace bytes for hrd_dirac_apply_batched with parity (HRD_EO needs one
+   odd FP32 temporary per right-hand side, plus the tile table). */
+size_t hrd_batched_workspace_bytes(const hrd_problem *probs, int nprob, hrd_parity parity);
+
+/* For every problem and right-hand side k: dst_k = X src_k with X as in
+   hrd_dirac_apply (parity HRD_EO, HRD_HOP_EO or HRD_HOP_OE; FP32 packed half
+   fields), with one persistent launch per hopping stage covering all
+   problems.  tune may be NULL (defaults).  Asynchronous. */
+hrd_status hrd_dirac_apply_batched(const hrd_problem *probs, int nprob, hrd_parity parity,
+                                   int dagger, const hrd_tune *tune, void *work,
+                                   size_t work_bytes, void *stream);
+
+/* Workspace bytes for hrd_cg_solve_batched. */
+size_t hrd_cg_batched_workspace_bytes(const hrd_problem *probs, int nprob);
+
+/* Independent mixed-precision reliable-update CG solves of A x_k = b_k for
+   every problem and right-hand side: src holds the FP64 packed even half
+   fields b_k, dst the FP64 x_k (initial guess on entry).  The FP32 operator
+   stages run batched (one launch per stage for all problems), reductions and
+   scalars are per right-hand side in FP64, converged right-hand sides are
+   masked out.  infos has one entry per right-hand side, in problem order.
+   Synchronises.  Returns HRD_ENOCONV if any system misses tol. */
+hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol, int maxiter,
+                                double delta, const hrd_tune *tune, void *work,
+                                size_t work_bytes, hrd_cg_info *infos, void *stream);
+
+/* Times candidate launch shapes of the batched hopping kernel on these
+   problems (work as for hrd_dirac_apply_batched with HRD_EO; src/dst are
+   overwritten) and writes the fastest to *best (median of 5 timed launches
+   per candidate; ties go to the smaller tile).  If cache_path is not NULL the
+   result is looked up in / appended to that JSON-lines file, keyed by the
+   GPU architecture and the problem list.  Synchronises. */
+hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, void *work,
+                                size_t work_bytes, const char *cache_path, hrd_tune *best,
+                                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRD_H */

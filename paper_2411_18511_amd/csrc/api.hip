@@ -1,0 +1,655 @@
+// C ABI of libhrd: argument validation, operator composition (D, D^, hop
+// blocks, daggers), level-1 linear algebra, the FP64 and mixed-precision CG
+// drivers and the fermion-force assembly.  Every computation runs in the HIP
+// kernels of this library; this file only validates, composes and launches.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "api_util.h"
+#include "kernels.h"
+
+namespace hrd {
+
+thread_local std::string g_last_error;
+
+hrd_status fail(hrd_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+hrd_status check_hip(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(HRD_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return HRD_OK;
+}
+
+hrd_status check_lattice(const hrd_lattice *lat)
+{
+    if (!lat) return fail(HRD_EINVAL, "lattice is NULL");
+    long long V = 1;
+    for (int i = 0; i < 4; i++) {
+        const int L = lat->dims[i];
+        if (L < 2 || (L & 1)) return fail(HRD_ESHAPE, "extent dims[%d] = %d must be even and >= 2", i, L);
+        V *= L;
+    }
+    if (V > (1LL << 30)) return fail(HRD_ESHAPE, "volume %lld exceeds 2^30 sites", V);
+    return HRD_OK;
+}
+
+hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
+{
+    if (rep != HRD_FUND && rep != HRD_ADJ) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
+    if (prec != HRD_F64 && prec != HRD_F32) return fail(HRD_EINVAL, "invalid precision %d", (int)prec);
+    return HRD_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (!a || !b || !na || !nb) return false;
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+size_t spinor_bytes(const hrd_lattice *lat, int rep, int prec, int nparity)
+{
+    const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    return (size_t)(V / 2) * spinor_site_bytes(rep, prec) * nparity;
+}
+
+size_t gauge_bytes(const hrd_lattice *lat, int rep, int prec)
+{
+    const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    return (size_t)V * 4 * link_bytes(rep, prec);
+}
+
+int ncomp_of(int rep) { return rep == HRD_FUND ? 8 : 12; }
+
+// D^ in (even half) -> out (even half), tmp: odd half of the same precision.
+hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, void *tmp,
+                      double m0, bool dag, double *norm_partials, hipStream_t st)
+{
+    const double m = 4.0 + m0;
+    HopArgs a{};
+    a.g = g;
+    a.U = U;
+    a.src = (const char *)in;
+    a.self = nullptr;
+    a.dst = (char *)tmp;
+    a.a = 0.0;
+    a.b = -0.5;
+    a.parity = 1;
+    hipError_t e = launch_hop(rep, prec, a, dag, false, false, false, st);
+    if (e != hipSuccess) return e;
+    a.src = (const char *)tmp;
+    a.self = (const char *)in;
+    a.dst = (char *)out;
+    a.a = m;
+    a.b = 0.5 / m;
+    a.parity = 0;
+    a.partials = norm_partials;
+    return launch_hop(rep, prec, a, dag, true, norm_partials != nullptr, false, st);
+}
+
+hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, const void *in, void *out,
+                           int target, bool dag, hipStream_t st)
+{
+    HopArgs a{};
+    a.g = g;
+    a.U = U;
+    a.src = (const char *)in;
+    a.dst = (char *)out;
+    a.a = 0.0;
+    a.b = -0.5;
+    a.parity = target;
+    return launch_hop(rep, prec, a, dag, false, false, false, st);
+}
+
+hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, double m0,
+                      bool dag, hipStream_t st)
+{
+    HopArgs a{};
+    a.g = g;
+    a.U = U;
+    a.src = (const char *)in;
+    a.dst = (char *)out;
+    a.a = 4.0 + m0;
+    a.b = -0.5;
+    a.half_bytes = (size_t)g.Vh * spinor_site_bytes(rep, prec);
+    return launch_hop(rep, prec, a, dag, true, false, true, st);
+}
+
+}  // namespace hrd
+
+using namespace hrd;
+
+namespace {
+
+// Workspace carving: 256-byte aligned sub-buffers.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    void *take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+    size_t used() const { return (off + 255) & ~(size_t)255; }
+};
+
+hrd_status read_scalars(const double *sc_dev, double *host, hipStream_t st)
+{
+    hrd_status s = check_hip(hipMemcpyAsync(host, sc_dev, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st),
+                             "hipMemcpyAsync(scalars)");
+    if (s != HRD_OK) return s;
+    return check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+struct CgBuffers {
+    // FP64 (both modes)
+    void *r64, *p64, *q64, *Ap64, *t64;
+    // FP32 (mixed)
+    void *r32, *p32, *q32, *Ap32, *t32;
+    double *partials, *sc;
+};
+
+size_t carve_cg(const hrd_lattice *lat, int rep, int mode, void *work, CgBuffers *b)
+{
+    Carver c(work);
+    const size_t h64 = spinor_bytes(lat, rep, HRD_F64, 1);
+    const size_t h32 = spinor_bytes(lat, rep, HRD_F32, 1);
+    const Geom g = make_geom(lat->dims);
+    const int nparts = std::max(hop_blocks(g), kRedBlocks) * 2;
+    CgBuffers t{};
+    t.r64 = c.take(h64);
+    t.q64 = c.take(h64);
+    t.Ap64 = c.take(h64);
+    t.t64 = c.take(h64);
+    if (mode == HRD_CG_F64) {
+        t.p64 = c.take(h64);
+    } else {
+        t.r32 = c.take(h32);
+        t.p32 = c.take(h32);
+        t.q32 = c.take(h32);
+        t.Ap32 = c.take(h32);
+        t.t32 = c.take(h32);
+    }
+    t.partials = (double *)c.take(sizeof(double) * nparts);
+    t.sc = (double *)c.take(sizeof(double) * S_COUNT);
+    if (b) *b = t;
+    return c.used();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hrd_last_error(void) { return g_last_error.c_str(); }
+
+const char *hrd_version(void) { return "hrd 0.1 (gfx950)"; }
+
+size_t hrd_spinor_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK || (nparity != 1 && nparity != 2)) return 0;
+    return spinor_bytes(lat, rep, prec, nparity);
+}
+
+size_t hrd_gauge_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    return gauge_bytes(lat, rep, prec);
+}
+
+hrd_status hrd_pack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U_nat, void *U, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (!U_nat || !U) return fail(HRD_EINVAL, "NULL field pointer");
+    const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_FUND ? 4 * 16 : 9 * 8);
+    if (overlap(U_nat, nat_bytes, U, gauge_bytes(lat, rep, prec))) return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_pack_gauge(rep, prec, g, U_nat, U, false, (hipStream_t)stream), "pack_gauge launch");
+}
+
+hrd_status hrd_unpack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, void *U_nat, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (!U_nat || !U) return fail(HRD_EINVAL, "NULL field pointer");
+    const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_FUND ? 4 * 16 : 9 * 8);
+    if (overlap(U_nat, nat_bytes, U, gauge_bytes(lat, rep, prec))) return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_pack_gauge(rep, prec, g, U_nat, const_cast<void *>(U), true, (hipStream_t)stream),
+                     "unpack_gauge launch");
+}
+
+hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj, hrd_prec prec_out, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(HRD_ADJ, prec_out));
+    if (!U_fund || !U_adj) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(U_fund, gauge_bytes(lat, HRD_FUND, HRD_F64), U_adj, gauge_bytes(lat, HRD_ADJ, prec_out)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_represent(prec_out, g, U_fund, U_adj, (hipStream_t)stream), "represent launch");
+}
+
+hrd_status hrd_represent_backward(const hrd_lattice *lat, const void *U_fund, const void *g_adj, void *G_fund,
+                                  void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    if (!U_fund || !g_adj || !G_fund) return fail(HRD_EINVAL, "NULL field pointer");
+    const size_t nf = gauge_bytes(lat, HRD_FUND, HRD_F64), na = gauge_bytes(lat, HRD_ADJ, HRD_F64);
+    if (overlap(G_fund, nf, U_fund, nf) || overlap(G_fund, nf, g_adj, na)) return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_represent_backward(g, U_fund, g_adj, G_fund, (hipStream_t)stream), "represent_backward launch");
+}
+
+hrd_status hrd_convert_gauge(const hrd_lattice *lat, hrd_rep rep, const void *U64, void *U32, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F32));
+    if (!U64 || !U32) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(U64, gauge_bytes(lat, rep, HRD_F64), U32, gauge_bytes(lat, rep, HRD_F32)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_convert_gauge(rep, g, U64, U32, (hipStream_t)stream), "convert_gauge launch");
+}
+
+hrd_status hrd_pack_spinor(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, hrd_sites sites, const void *psi_nat,
+                           void *psi, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (sites < HRD_SITES_ALL || sites > HRD_SITES_ODD) return fail(HRD_EINVAL, "invalid site subset %d", (int)sites);
+    if (!psi_nat || !psi) return fail(HRD_EINVAL, "NULL field pointer");
+    const int np = sites == HRD_SITES_ALL ? 2 : 1;
+    if (overlap(psi_nat, spinor_bytes(lat, rep, HRD_F64, 2), psi, spinor_bytes(lat, rep, prec, np)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_pack_spinor(rep, prec, sites, g, psi_nat, psi, false, (hipStream_t)stream), "pack_spinor launch");
+}
+
+hrd_status hrd_unpack_spinor(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, hrd_sites sites, const void *psi,
+                             void *psi_nat, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (sites < HRD_SITES_ALL || sites > HRD_SITES_ODD) return fail(HRD_EINVAL, "invalid site subset %d", (int)sites);
+    if (!psi_nat || !psi) return fail(HRD_EINVAL, "NULL field pointer");
+    const int np = sites == HRD_SITES_ALL ? 2 : 1;
+    if (overlap(psi_nat, spinor_bytes(lat, rep, HRD_F64, 2), psi, spinor_bytes(lat, rep, prec, np)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_pack_spinor(rep, prec, sites, g, psi_nat, const_cast<void *>(psi), true, (hipStream_t)stream),
+                     "unpack_spinor launch");
+}
+
+hrd_status hrd_convert_spinor(const hrd_lattice *lat, hrd_rep rep, int nparity, int to_f32, const void *in, void *out,
+                              void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (nparity != 1 && nparity != 2) return fail(HRD_EINVAL, "nparity must be 1 or 2");
+    if (!in || !out) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(in, spinor_bytes(lat, rep, to_f32 ? HRD_F64 : HRD_F32, nparity), out,
+                spinor_bytes(lat, rep, to_f32 ? HRD_F32 : HRD_F64, nparity)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_convert_spinor(g.Vh, nparity, ncomp_of(rep), to_f32 != 0, in, out, (hipStream_t)stream),
+                     "convert_spinor launch");
+}
+
+size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, hrd_parity parity)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    return parity == HRD_EO ? spinor_bytes(lat, rep, prec, 1) : 0;
+}
+
+hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *psi,
+                           void *out, double m0, hrd_parity parity, int dagger, void *work, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (parity < HRD_FULL || parity > HRD_HOP_OE) return fail(HRD_EINVAL, "invalid parity mode %d", (int)parity);
+    if (!U || !psi || !out) return fail(HRD_EINVAL, "NULL field pointer");
+    if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return fail(HRD_EINVAL, "m0 = %g is not finite or makes 4 + m0 zero", m0);
+    const int np = parity == HRD_FULL ? 2 : 1;
+    const size_t sb = spinor_bytes(lat, rep, prec, np);
+    const size_t ub = gauge_bytes(lat, rep, prec);
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub)) return fail(HRD_EALIAS, "output overlaps an input");
+    if (parity == HRD_EO) {
+        if (!work) return fail(HRD_EINVAL, "HRD_EO needs a workspace of hrd_dirac_workspace_bytes bytes");
+        const size_t wb = spinor_bytes(lat, rep, prec, 1);
+        if (overlap(work, wb, psi, sb) || overlap(work, wb, out, sb) || overlap(work, wb, U, ub))
+            return fail(HRD_EALIAS, "workspace overlaps a field");
+    }
+    const Geom g = make_geom(lat->dims);
+    const hipStream_t st = (hipStream_t)stream;
+    const bool dag = dagger != 0;
+    hipError_t e = hipSuccess;
+    switch (parity) {
+        case HRD_FULL: e = apply_full(rep, prec, g, U, psi, out, m0, dag, st); break;
+        case HRD_EO: e = apply_dhat(rep, prec, g, U, psi, out, work, m0, dag, nullptr, st); break;
+        case HRD_HOP_EO: e = apply_hop_block(rep, prec, g, U, psi, out, 0, dag, st); break;
+        case HRD_HOP_OE: e = apply_hop_block(rep, prec, g, U, psi, out, 1, dag, st); break;
+    }
+    return check_hip(e, "dirac_apply launch");
+}
+
+size_t hrd_blas_workspace_bytes(void) { return sizeof(double) * (2 * kRedBlocks + 8); }
+
+static hrd_status blas_common(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, void *work)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (nparity != 1 && nparity != 2) return fail(HRD_EINVAL, "nparity must be 1 or 2");
+    if (!work) return fail(HRD_EINVAL, "NULL workspace");
+    return HRD_OK;
+}
+
+static hrd_status finish_reduction(double *partials, int ncol, double *result, hipStream_t st)
+{
+    double *sums = partials + 2 * kRedBlocks;
+    HRD_TRY(check_hip(launch_finalize(partials, kRedBlocks, ncol, sums, st), "finalize launch"));
+    HRD_TRY(check_hip(hipMemcpyAsync(result, sums, sizeof(double) * ncol, hipMemcpyDeviceToHost, st), "hipMemcpyAsync"));
+    return check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+hrd_status hrd_blas_dot(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, const void *a, const void *b,
+                        double *result, void *work, void *stream)
+{
+    HRD_TRY(blas_common(lat, rep, prec, nparity, work));
+    if (!a || !b || !result) return fail(HRD_EINVAL, "NULL pointer");
+    const size_t n16 = spinor_bytes(lat, rep, prec, nparity) / 16;
+    const hipStream_t st = (hipStream_t)stream;
+    double *parts = (double *)work;
+    HRD_TRY(check_hip(launch_dot_partials(prec, n16, a, b, parts, st), "dot launch"));
+    return finish_reduction(parts, 2, result, st);
+}
+
+hrd_status hrd_blas_norm2(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, const void *a,
+                          double *result, void *work, void *stream)
+{
+    HRD_TRY(blas_common(lat, rep, prec, nparity, work));
+    if (!a || !result) return fail(HRD_EINVAL, "NULL pointer");
+    const size_t n16 = spinor_bytes(lat, rep, prec, nparity) / 16;
+    const hipStream_t st = (hipStream_t)stream;
+    double *parts = (double *)work;
+    HRD_TRY(check_hip(launch_norm_partials(prec, n16, a, parts, st), "norm launch"));
+    return finish_reduction(parts, 1, result, st);
+}
+
+hrd_status hrd_blas_axpy(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, double a_re, double a_im,
+                         const void *x, void *y, double *result, void *work, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (nparity != 1 && nparity != 2) return fail(HRD_EINVAL, "nparity must be 1 or 2");
+    if (!x || !y) return fail(HRD_EINVAL, "NULL pointer");
+    if (result && !work) return fail(HRD_EINVAL, "a fused norm needs a workspace");
+    const size_t bytes = spinor_bytes(lat, rep, prec, nparity);
+    if (overlap(x, bytes, y, bytes) && x != y) return fail(HRD_EALIAS, "x and y partially overlap");
+    const size_t n16 = bytes / 16;
+    const hipStream_t st = (hipStream_t)stream;
+    double *parts = result ? (double *)work : nullptr;
+    HRD_TRY(check_hip(launch_axpy(prec, n16, a_re, a_im, x, y, parts, st), "axpy launch"));
+    if (!result) return HRD_OK;
+    return finish_reduction(parts, 1, result, st);
+}
+
+hrd_status hrd_blas_xpay(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, const void *x, double a_re,
+                         double a_im, void *y, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (nparity != 1 && nparity != 2) return fail(HRD_EINVAL, "nparity must be 1 or 2");
+    if (!x || !y) return fail(HRD_EINVAL, "NULL pointer");
+    const size_t bytes = spinor_bytes(lat, rep, prec, nparity);
+    if (overlap(x, bytes, y, bytes) && x != y) return fail(HRD_EALIAS, "x and y partially overlap");
+    return check_hip(launch_xpay(prec, bytes / 16, x, a_re, a_im, y, (hipStream_t)stream), "xpay launch");
+}
+
+size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK) return 0;
+    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED) return 0;
+    return carve_cg(lat, rep, mode, nullptr, nullptr);
+}
+
+hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, const void *U64, const void *U32,
+                        const void *b, void *x, double m0, double tol, int maxiter, double delta, void *work,
+                        size_t work_bytes, hrd_cg_info *info, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    hrd_cg_info inf{};
+    auto finish = [&](hrd_status s) {
+        inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
+        return s;
+    };
+    {
+        hrd_status s = check_lattice(lat);
+        if (s == HRD_OK) s = check_rep_prec(rep, HRD_F64);
+        if (s != HRD_OK) return finish(s);
+    }
+    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED) return finish(fail(HRD_EINVAL, "invalid CG mode %d", (int)mode));
+    if (!U64 || !b || !x || !work) return finish(fail(HRD_EINVAL, "NULL pointer"));
+    if (mode == HRD_CG_MIXED && !U32) return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 gauge field"));
+    if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(HRD_EINVAL, "tol must be positive"));
+    if (maxiter < 0) return finish(fail(HRD_EINVAL, "maxiter must be >= 0"));
+    const size_t need = carve_cg(lat, rep, mode, nullptr, nullptr);
+    if (work_bytes < need) return finish(fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need));
+    const size_t h64 = spinor_bytes(lat, rep, HRD_F64, 1);
+    if (overlap(x, h64, b, h64)) return finish(fail(HRD_EALIAS, "x overlaps b"));
+    if (overlap(work, need, x, h64) || overlap(work, need, b, h64) ||
+        overlap(work, need, U64, gauge_bytes(lat, rep, HRD_F64)))
+        return finish(fail(HRD_EALIAS, "workspace overlaps a field"));
+    if (delta <= 0.0) delta = 0.1;
+
+    CgBuffers w;
+    carve_cg(lat, rep, mode, work, &w);
+    const Geom g = make_geom(lat->dims);
+    const hipStream_t st = (hipStream_t)stream;
+    const int nc = ncomp_of(rep);
+    const size_t n64 = h64 / 16;
+    const size_t n32 = spinor_bytes(lat, rep, HRD_F32, 1) / 16;
+    const int hb = hop_blocks(g);
+    double sc[S_COUNT];
+
+#define CG_HIP(expr, what)                                        \
+    do {                                                          \
+        hrd_status s_ = check_hip((expr), what);                  \
+        if (s_ != HRD_OK) return finish(s_);                      \
+    } while (0)
+
+    // ||b||^2
+    CG_HIP(launch_zero(sizeof(double) * S_COUNT, w.sc, st), "zero");
+    CG_HIP(launch_norm_partials(HRD_F64, n64, b, w.partials, st), "norm(b)");
+    CG_HIP(launch_finalize(w.partials, kRedBlocks, 1, w.sc + S_BB, st), "finalize");
+    {
+        hrd_status s = read_scalars(w.sc, sc, st);
+        if (s != HRD_OK) return finish(s);
+    }
+    const double bb = sc[S_BB];
+    if (!std::isfinite(bb)) return finish(fail(HRD_EBREAKDOWN, "source has non-finite entries"));
+    if (bb == 0.0) {
+        CG_HIP(launch_zero(h64, x, st), "zero x");
+        CG_HIP(hipStreamSynchronize(st), "sync");
+        return finish(HRD_OK);
+    }
+    const double bnorm = std::sqrt(bb);
+    const double target = tol * bnorm;
+
+    // r = b - A x (FP64), rr = ||r||^2
+    auto true_residual = [&](void) -> hrd_status {
+        hipError_t e = apply_dhat(rep, HRD_F64, g, U64, x, w.q64, w.t64, m0, false, nullptr, st);
+        if (e == hipSuccess) e = apply_dhat(rep, HRD_F64, g, U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st);
+        if (e == hipSuccess) {
+            if (mode == HRD_CG_F64) e = launch_cg_residual64(n64, b, w.Ap64, w.r64, w.partials, st);
+            else e = launch_cg_residual_mixed(g.Vh, nc, b, w.Ap64, w.r64, w.r32, w.partials, st);
+        }
+        if (e == hipSuccess) e = launch_finalize(w.partials, kRedBlocks, 1, w.sc + S_RR, st);
+        hrd_status s = check_hip(e, "true residual");
+        if (s != HRD_OK) return s;
+        return read_scalars(w.sc, sc, st);
+    };
+
+    {
+        hrd_status s = true_residual();
+        if (s != HRD_OK) return finish(s);
+    }
+    double rr = sc[S_RR];
+    inf.true_rel_residual = std::sqrt(rr) / bnorm;
+    inf.iterated_rel_residual = inf.true_rel_residual;
+    if (!std::isfinite(rr)) return finish(fail(HRD_EBREAKDOWN, "initial residual is not finite"));
+    if (std::sqrt(rr) <= target) return finish(HRD_OK);
+
+    if (mode == HRD_CG_F64) {
+        CG_HIP(launch_copy(h64, w.r64, w.p64, st), "copy");
+        while (inf.iters < maxiter) {
+            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st), "D^ p");
+            CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
+            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st), "D^+ q");
+            CG_HIP(launch_cg_update_r(HRD_F64, n64, w.r64, w.Ap64, w.sc, w.partials, st), "update r");
+            CG_HIP(launch_cg_beta(w.partials, kRedBlocks, w.sc, st), "beta");
+            CG_HIP(launch_cg_update_xp64(n64, x, w.p64, w.r64, w.sc, st), "update x, p");
+            inf.iters++;
+            {
+                hrd_status s = read_scalars(w.sc, sc, st);
+                if (s != HRD_OK) return finish(s);
+            }
+            if (sc[S_FLAG] != 0.0)
+                return finish(fail(HRD_EBREAKDOWN, "CG breakdown at iteration %d (pAp = %g, rr = %g)", inf.iters,
+                                   sc[S_PAP], sc[S_RRNEW]));
+            rr = sc[S_RR];
+            inf.iterated_rel_residual = std::sqrt(rr) / bnorm;
+            if (std::sqrt(rr) <= target) {
+                hrd_status s = true_residual();
+                if (s != HRD_OK) return finish(s);
+                rr = sc[S_RR];
+                inf.true_rel_residual = std::sqrt(rr) / bnorm;
+                if (std::sqrt(rr) <= target) return finish(HRD_OK);
+                inf.restarts++;
+                CG_HIP(launch_copy(h64, w.r64, w.p64, st), "copy");
+            }
+        }
+        hrd_status s = true_residual();
+        if (s != HRD_OK) return finish(s);
+        inf.true_rel_residual = std::sqrt(sc[S_RR]) / bnorm;
+        return finish(fail(HRD_ENOCONV, "CG did not converge in %d iterations (residual %g)", maxiter,
+                           inf.true_rel_residual));
+    }
+
+    // mixed precision with reliable updates
+    const size_t h32 = spinor_bytes(lat, rep, HRD_F32, 1);
+    CG_HIP(launch_copy(h32, w.r32, w.p32, st), "copy");
+    double rmax = std::sqrt(rr);
+    while (inf.iters < maxiter) {
+        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.p32, w.q32, w.t32, m0, false, w.partials, st), "D^ p");
+        CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
+        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.q32, w.Ap32, w.t32, m0, true, nullptr, st), "D^+ q");
+        CG_HIP(launch_cg_update_r(HRD_F32, n32, w.r32, w.Ap32, w.sc, w.partials, st), "update r");
+        CG_HIP(launch_cg_beta(w.partials, kRedBlocks, w.sc, st), "beta");
+        inf.iters++;
+        {
+            hrd_status s = read_scalars(w.sc, sc, st);
+            if (s != HRD_OK) return finish(s);
+        }
+        if (sc[S_FLAG] != 0.0)
+            return finish(fail(HRD_EBREAKDOWN, "CG breakdown at iteration %d (pAp = %g, rr = %g)", inf.iters,
+                               sc[S_PAP], sc[S_RRNEW]));
+        const double rnew = std::sqrt(sc[S_RR]);
+        inf.iterated_rel_residual = rnew / bnorm;
+        rmax = std::max(rmax, rnew);
+        if (rnew < delta * rmax || rnew <= target) {
+            // x += alpha p ; then r = b - A x in FP64, r32 = f32(r), beta from the new residual
+            CG_HIP(launch_cg_update_x_mixed(g.Vh, nc, x, w.p32, w.sc, st), "update x");
+            hrd_status s = true_residual();
+            if (s != HRD_OK) return finish(s);
+            inf.reliable_updates++;
+            const double rt = std::sqrt(sc[S_RR]);
+            inf.true_rel_residual = rt / bnorm;
+            if (!std::isfinite(rt)) return finish(fail(HRD_EBREAKDOWN, "non-finite residual"));
+            if (rt <= target) return finish(HRD_OK);
+            rmax = rt;
+            CG_HIP(launch_cg_update_p32(n32, w.p32, w.r32, w.sc, st), "update p");
+        } else {
+            CG_HIP(launch_cg_update_xp_mixed(g.Vh, nc, x, w.p32, w.r32, w.sc, st), "update x, p");
+        }
+    }
+    {
+        hrd_status s = true_residual();
+        if (s != HRD_OK) return finish(s);
+    }
+    inf.true_rel_residual = std::sqrt(sc[S_RR]) / bnorm;
+    return finish(fail(HRD_ENOCONV, "mixed CG did not converge in %d iterations (residual %g)", maxiter,
+                       inf.true_rel_residual));
+#undef CG_HIP
+}
+
+hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *X,
+                           const void *Y, void *F, double scale, void *stream)
+{
+    (void)U;
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (prec != HRD_F64) return fail(HRD_EINVAL, "the force is computed in FP64 only");
+    if (!X || !Y || !F) return fail(HRD_EINVAL, "NULL field pointer");
+    if (!std::isfinite(scale)) return fail(HRD_EINVAL, "scale is not finite");
+    const size_t sb = spinor_bytes(lat, rep, HRD_F64, 2), fb = gauge_bytes(lat, rep, HRD_F64);
+    if (overlap(F, fb, X, sb) || overlap(F, fb, Y, sb)) return fail(HRD_EALIAS, "output overlaps an input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_force(rep, g, X, Y, F, scale, (hipStream_t)stream), "force launch");
+}
+
+size_t hrd_action_force_workspace_bytes(const hrd_lattice *lat, hrd_rep rep)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK) return 0;
+    return 2 * spinor_bytes(lat, rep, HRD_F64, 2) + 256;
+}
+
+hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U, const void *xi, void *F, double m0,
+                            double scale, void *work, size_t work_bytes, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (!U || !xi || !F || !work) return fail(HRD_EINVAL, "NULL pointer");
+    if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return fail(HRD_EINVAL, "invalid m0 %g", m0);
+    if (!std::isfinite(scale)) return fail(HRD_EINVAL, "scale is not finite");
+    const size_t need = 2 * spinor_bytes(lat, rep, HRD_F64, 2);
+    if (work_bytes < need) return fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need);
+    const size_t fb = gauge_bytes(lat, rep, HRD_F64), h = spinor_bytes(lat, rep, HRD_F64, 1);
+    if (overlap(F, fb, xi, h) || overlap(F, fb, U, fb) || overlap(work, need, F, fb) || overlap(work, need, xi, h) ||
+        overlap(work, need, U, fb))
+        return fail(HRD_EALIAS, "buffers overlap");
+    const Geom g = make_geom(lat->dims);
+    const hipStream_t st = (hipStream_t)stream;
+    char *X = (char *)work;
+    char *Y = X + 2 * h;
+    // Y = (xi, D_oe xi) ; X = (eta, (D_eo)^+ eta) with eta = D^ xi
+    hipError_t e = launch_copy(h, xi, Y, st);
+    if (e == hipSuccess) e = apply_hop_block(rep, HRD_F64, g, U, xi, Y + h, 1, false, st);
+    // eta = D^ xi, using the odd half of X as the temporary, then the odd half of X
+    if (e == hipSuccess) e = apply_dhat(rep, HRD_F64, g, U, xi, X, X + h, m0, false, nullptr, st);
+    if (e == hipSuccess) e = apply_hop_block(rep, HRD_F64, g, U, X, X + h, 1, true, st);
+    if (e == hipSuccess) e = launch_force(rep, g, X, Y, F, scale * 2.0 / (4.0 + m0), st);
+    return check_hip(e, "action force");
+}
+
+}  // extern "C"

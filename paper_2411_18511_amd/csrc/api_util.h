@@ -1,0 +1,37 @@
+// Host-side helpers shared by the C-ABI implementation files: error
+// reporting, argument checks and the operator compositions.
+#pragma once
+
+#include <algorithm>
+
+#include "kernels.h"
+
+#define HRD_TRY(expr)                       \
+    do {                                    \
+        const hrd_status s__ = (expr);      \
+        if (s__ != HRD_OK) return s__;      \
+    } while (0)
+
+namespace hrd {
+
+hrd_status fail(hrd_status st, const char *fmt, ...);
+hrd_status check_hip(hipError_t e, const char *what);
+hrd_status check_lattice(const hrd_lattice *lat);
+hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec);
+bool overlap(const void *a, size_t na, const void *b, size_t nb);
+size_t spinor_bytes(const hrd_lattice *lat, int rep, int prec, int nparity);
+size_t gauge_bytes(const hrd_lattice *lat, int rep, int prec);
+int ncomp_of(int rep);
+
+// D^ (dag: D^+) of an even half field; tmp is an odd half field; optional
+// ||out||^2 partials (hop_blocks(g) of them).
+hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, void *tmp,
+                      double m0, bool dag, double *norm_partials, hipStream_t st);
+// out (parity target) = D_{target,1-target} in, or its g5-conjugate.
+hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, const void *in, void *out,
+                           int target, bool dag, hipStream_t st);
+// out = D in on full-lattice fields.
+hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, double m0,
+                      bool dag, hipStream_t st);
+
+}  // namespace hrd

@@ -1,0 +1,440 @@
+// Level-1 linear algebra on packed spinor fields and the fused vector stages
+// of the conjugate-gradient solvers.  Fields are viewed as arrays of 16-byte
+// elements (one complex128, or two complex64); the layouts of hrd.h keep
+// complex pairs inside one element, so element-wise kernels and reductions do
+// not need the site structure, except where FP64 and FP32 fields meet.
+//
+// Reductions: a fixed grid of kRedBlocks blocks walks the field with a
+// grid-stride loop, each block writes its partial (wave64 butterfly + LDS),
+// and one block sums the partials in a fixed order — bitwise reproducible,
+// always accumulated in FP64.
+#include "kernels.h"
+
+namespace hrd {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+template <typename R>
+struct Elem;
+template <>
+struct Elem<double> {
+    static constexpr int C = 1;
+    __device__ __forceinline__ static void load(const void *p, size_t i, Cx<double> (&c)[1])
+    {
+        const double2 v = reinterpret_cast<const double2 *>(p)[i];
+        c[0] = {v.x, v.y};
+    }
+    __device__ __forceinline__ static void store(void *p, size_t i, const Cx<double> (&c)[1])
+    {
+        reinterpret_cast<double2 *>(p)[i] = make_double2(c[0].re, c[0].im);
+    }
+};
+template <>
+struct Elem<float> {
+    static constexpr int C = 2;
+    __device__ __forceinline__ static void load(const void *p, size_t i, Cx<float> (&c)[2])
+    {
+        const float4 v = reinterpret_cast<const float4 *>(p)[i];
+        c[0] = {v.x, v.y};
+        c[1] = {v.z, v.w};
+    }
+    __device__ __forceinline__ static void store(void *p, size_t i, const Cx<float> (&c)[2])
+    {
+        reinterpret_cast<float4 *>(p)[i] = make_float4(c[0].re, c[0].im, c[1].re, c[1].im);
+    }
+};
+
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(size_t n, const void *a, const void *b, double *partials)
+{
+    constexpr int C = Elem<R>::C;
+    double re = 0, im = 0;
+    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+        Cx<R> x[C], y[C];
+        Elem<R>::load(a, i, x);
+        Elem<R>::load(b, i, y);
+#pragma unroll
+        for (int k = 0; k < C; k++) {
+            re += (double)x[k].re * y[k].re + (double)x[k].im * y[k].im;
+            im += (double)x[k].re * y[k].im - (double)x[k].im * y[k].re;
+        }
+    }
+    block_sum2<kRedThreads>(re, im);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = re;
+        partials[2 * blockIdx.x + 1] = im;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void norm_kernel(size_t n, const void *a, double *partials)
+{
+    constexpr int C = Elem<R>::C;
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+        Cx<R> x[C];
+        Elem<R>::load(a, i, x);
+#pragma unroll
+        for (int k = 0; k < C; k++) s += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
+    }
+    s = block_sum<kRedThreads>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// y <- y + a x, optional ||y||^2 partials
+template <typename R, bool NORM>
+__global__ __launch_bounds__(kRedThreads) void axpy_kernel(size_t n, double ar, double ai, const void *x, void *y,
+                                                          double *partials)
+{
+    constexpr int C = Elem<R>::C;
+    const R cr = (R)ar, ci = (R)ai;
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+        Cx<R> u[C], v[C];
+        Elem<R>::load(x, i, u);
+        Elem<R>::load(y, i, v);
+#pragma unroll
+        for (int k = 0; k < C; k++) {
+            v[k] = cfma(Cx<R>{cr, ci}, u[k], v[k]);
+            if (NORM) s += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+        }
+        Elem<R>::store(y, i, v);
+    }
+    if constexpr (NORM) {
+        s = block_sum<kRedThreads>(s);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// y <- x + a y
+template <typename R>
+__global__ __launch_bounds__(kBlock) void xpay_kernel(size_t n, const void *x, double ar, double ai, void *y)
+{
+    constexpr int C = Elem<R>::C;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Cx<R> u[C], v[C];
+    Elem<R>::load(x, i, u);
+    Elem<R>::load(y, i, v);
+#pragma unroll
+    for (int k = 0; k < C; k++) v[k] = cfma(Cx<R>{(R)ar, (R)ai}, v[k], u[k]);
+    Elem<R>::store(y, i, v);
+}
+
+constexpr int kFinThreads = 1024;
+
+// Column sums of a [nblk][ncol] table, fixed order.
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double *partials, int nblk, int ncol, double *sums)
+{
+    for (int c = 0; c < ncol; c++) {
+        double s = 0;
+        for (int k = threadIdx.x; k < nblk; k += kFinThreads) s += partials[(size_t)k * ncol + c];
+        s = block_sum<kFinThreads>(s);
+        if (threadIdx.x == 0) sums[c] = s;
+    }
+}
+
+__device__ __forceinline__ double fixed_sum(const double *partials, int nblk)
+{
+    double s = 0;
+    for (int k = threadIdx.x; k < nblk; k += kFinThreads) s += partials[k];
+    return block_sum<kFinThreads>(s);
+}
+
+__global__ __launch_bounds__(kFinThreads) void cg_alpha_kernel(const double *partials, int nblk, double *sc)
+{
+    const double pap = fixed_sum(partials, nblk);
+    if (threadIdx.x == 0) {
+        sc[S_PAP] = pap;
+        if (!(pap > 0.0) || !isfinite(pap)) {
+            sc[S_FLAG] = 1.0;
+            sc[S_ALPHA] = 0.0;
+        } else {
+            sc[S_ALPHA] = sc[S_RR] / pap;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void cg_beta_kernel(const double *partials, int nblk, double *sc)
+{
+    const double rr = fixed_sum(partials, nblk);
+    if (threadIdx.x == 0) {
+        sc[S_RRNEW] = rr;
+        if (!isfinite(rr)) {
+            sc[S_FLAG] = 2.0;
+            sc[S_BETA] = 0.0;
+        } else {
+            sc[S_BETA] = (sc[S_RR] > 0.0) ? rr / sc[S_RR] : 0.0;
+        }
+        sc[S_RROLD] = sc[S_RR];
+        sc[S_RR] = rr;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void cg_update_r_kernel(size_t n, void *r, const void *Ap, const double *sc,
+                                                                 double *partials)
+{
+    constexpr int C = Elem<R>::C;
+    const R alpha = (R)sc[S_ALPHA];
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+        Cx<R> u[C], v[C];
+        Elem<R>::load(r, i, u);
+        Elem<R>::load(Ap, i, v);
+#pragma unroll
+        for (int k = 0; k < C; k++) {
+            u[k] = Cx<R>{u[k].re - alpha * v[k].re, u[k].im - alpha * v[k].im};
+            s += (double)u[k].re * u[k].re + (double)u[k].im * u[k].im;
+        }
+        Elem<R>::store(r, i, u);
+    }
+    s = block_sum<kRedThreads>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void cg_update_xp64_kernel(size_t n, void *x, void *p, const void *r, const double *sc)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = sc[S_ALPHA], beta = sc[S_BETA];
+    double2 *X = reinterpret_cast<double2 *>(x);
+    double2 *P = reinterpret_cast<double2 *>(p);
+    const double2 rv = reinterpret_cast<const double2 *>(r)[i];
+    const double2 pv = P[i];
+    double2 xv = X[i];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    X[i] = xv;
+    P[i] = make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+}
+
+// thread per (F32 plane q, site j); F64 planes 2q, 2q+1
+__global__ __launch_bounds__(kBlock) void cg_update_xp_mixed_kernel(int Vh, int npl, void *x64, void *p32, const void *r32,
+                                                                   const double *sc)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)npl * Vh) return;
+    const int q = (int)(t / Vh);
+    const int j = (int)(t - (long)q * Vh);
+    const double alpha = sc[S_ALPHA];
+    const float beta = (float)sc[S_BETA];
+    float4 *P = reinterpret_cast<float4 *>(p32);
+    double2 *X = reinterpret_cast<double2 *>(x64);
+    const float4 pv = P[t];
+    const float4 rv = reinterpret_cast<const float4 *>(r32)[t];
+    const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
+    double2 x0 = X[i0], x1 = X[i1];
+    x0.x += alpha * (double)pv.x;
+    x0.y += alpha * (double)pv.y;
+    x1.x += alpha * (double)pv.z;
+    x1.y += alpha * (double)pv.w;
+    X[i0] = x0;
+    X[i1] = x1;
+    P[t] = make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+}
+
+__global__ __launch_bounds__(kBlock) void cg_update_x_mixed_kernel(int Vh, int npl, void *x64, const void *p32,
+                                                                  const double *sc)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)npl * Vh) return;
+    const int q = (int)(t / Vh);
+    const int j = (int)(t - (long)q * Vh);
+    const double alpha = sc[S_ALPHA];
+    double2 *X = reinterpret_cast<double2 *>(x64);
+    const float4 pv = reinterpret_cast<const float4 *>(p32)[t];
+    const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
+    double2 x0 = X[i0], x1 = X[i1];
+    x0.x += alpha * (double)pv.x;
+    x0.y += alpha * (double)pv.y;
+    x1.x += alpha * (double)pv.z;
+    x1.y += alpha * (double)pv.w;
+    X[i0] = x0;
+    X[i1] = x1;
+}
+
+__global__ __launch_bounds__(kBlock) void cg_update_p32_kernel(size_t n, void *p32, const void *r32, const double *sc)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float beta = (float)(sc[S_RROLD] > 0.0 ? sc[S_RR] / sc[S_RROLD] : 0.0);
+    float4 *P = reinterpret_cast<float4 *>(p32);
+    const float4 pv = P[i];
+    const float4 rv = reinterpret_cast<const float4 *>(r32)[i];
+    P[i] = make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+}
+
+__global__ __launch_bounds__(kRedThreads) void cg_residual_mixed_kernel(int Vh, int npl, const void *b, const void *Ax,
+                                                                       void *r64, void *r32, double *partials)
+{
+    const long n = (long)npl * Vh;
+    double s = 0;
+    for (long t = (long)blockIdx.x * kRedThreads + threadIdx.x; t < n; t += (long)gridDim.x * kRedThreads) {
+        const int q = (int)(t / Vh);
+        const int j = (int)(t - (long)q * Vh);
+        const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
+        const double2 b0 = reinterpret_cast<const double2 *>(b)[i0];
+        const double2 b1 = reinterpret_cast<const double2 *>(b)[i1];
+        const double2 a0 = reinterpret_cast<const double2 *>(Ax)[i0];
+        const double2 a1 = reinterpret_cast<const double2 *>(Ax)[i1];
+        const double2 r0 = make_double2(b0.x - a0.x, b0.y - a0.y);
+        const double2 r1 = make_double2(b1.x - a1.x, b1.y - a1.y);
+        reinterpret_cast<double2 *>(r64)[i0] = r0;
+        reinterpret_cast<double2 *>(r64)[i1] = r1;
+        reinterpret_cast<float4 *>(r32)[t] = make_float4((float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y);
+        s += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
+    }
+    s = block_sum<kRedThreads>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void cg_residual64_kernel(size_t n, const void *b, const void *Ax, void *r,
+                                                                   double *partials)
+{
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+        const double2 bv = reinterpret_cast<const double2 *>(b)[i];
+        const double2 av = reinterpret_cast<const double2 *>(Ax)[i];
+        const double2 rv = make_double2(bv.x - av.x, bv.y - av.y);
+        reinterpret_cast<double2 *>(r)[i] = rv;
+        s += rv.x * rv.x + rv.y * rv.y;
+    }
+    s = block_sum<kRedThreads>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void copy16_kernel(size_t n, const float4 *src, float4 *dst)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void zero16_kernel(size_t n, float4 *dst)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+inline dim3 grid_for(size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+}  // namespace
+
+hipError_t launch_dot_partials(int prec, size_t n16, const void *a, const void *b, double *partials, hipStream_t st)
+{
+    if (prec == HRD_F64) hipLaunchKernelGGL(dot_kernel<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, a, b, partials);
+    else hipLaunchKernelGGL(dot_kernel<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, a, b, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_partials(int prec, size_t n16, const void *a, double *partials, hipStream_t st)
+{
+    if (prec == HRD_F64) hipLaunchKernelGGL(norm_kernel<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, a, partials);
+    else hipLaunchKernelGGL(norm_kernel<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, a, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int prec, size_t n16, double ar, double ai, const void *x, void *y, double *partials,
+                       hipStream_t st)
+{
+    const dim3 g(kRedBlocks), b(kRedThreads);
+    if (prec == HRD_F64) {
+        if (partials) hipLaunchKernelGGL((axpy_kernel<double, true>), g, b, 0, st, n16, ar, ai, x, y, partials);
+        else hipLaunchKernelGGL((axpy_kernel<double, false>), g, b, 0, st, n16, ar, ai, x, y, partials);
+    } else {
+        if (partials) hipLaunchKernelGGL((axpy_kernel<float, true>), g, b, 0, st, n16, ar, ai, x, y, partials);
+        else hipLaunchKernelGGL((axpy_kernel<float, false>), g, b, 0, st, n16, ar, ai, x, y, partials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_xpay(int prec, size_t n16, const void *x, double ar, double ai, void *y, hipStream_t st)
+{
+    if (prec == HRD_F64) hipLaunchKernelGGL(xpay_kernel<double>, grid_for(n16), dim3(kBlock), 0, st, n16, x, ar, ai, y);
+    else hipLaunchKernelGGL(xpay_kernel<float>, grid_for(n16), dim3(kBlock), 0, st, n16, x, ar, ai, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nblk, int ncol, double *sums, hipStream_t st)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, st, partials, nblk, ncol, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kFinThreads), 0, st, partials, nblk, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const double *partials, int nblk, double *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(kFinThreads), 0, st, partials, nblk, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_r(int prec, size_t n16, void *r, const void *Ap, const double *sc, double *partials,
+                              hipStream_t st)
+{
+    if (prec == HRD_F64) hipLaunchKernelGGL(cg_update_r_kernel<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, r, Ap, sc, partials);
+    else hipLaunchKernelGGL(cg_update_r_kernel<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, r, Ap, sc, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_xp64(size_t n16, void *x, void *p, const void *r, const double *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_update_xp64_kernel, grid_for(n16), dim3(kBlock), 0, st, n16, x, p, r, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_xp_mixed(int Vh, int ncomp, void *x64, void *p32, const void *r32, const double *sc,
+                                     hipStream_t st)
+{
+    const int npl = ncomp / 2;
+    hipLaunchKernelGGL(cg_update_xp_mixed_kernel, grid_for((size_t)npl * Vh), dim3(kBlock), 0, st, Vh, npl, x64, p32, r32, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_x_mixed(int Vh, int ncomp, void *x64, const void *p32, const double *sc, hipStream_t st)
+{
+    const int npl = ncomp / 2;
+    hipLaunchKernelGGL(cg_update_x_mixed_kernel, grid_for((size_t)npl * Vh), dim3(kBlock), 0, st, Vh, npl, x64, p32, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_p32(size_t n16, void *p32, const void *r32, const double *sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_update_p32_kernel, grid_for(n16), dim3(kBlock), 0, st, n16, p32, r32, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_residual_mixed(int Vh, int ncomp, const void *b, const void *Ax, void *r64, void *r32,
+                                    double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_residual_mixed_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, st, Vh, ncomp / 2, b, Ax, r64, r32, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_residual64(size_t n16, const void *b, const void *Ax, void *r, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(cg_residual64_kernel, dim3(kRedBlocks), dim3(kRedThreads), 0, st, n16, b, Ax, r, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(size_t bytes, const void *src, void *dst, hipStream_t st)
+{
+    const size_t n = bytes / 16;
+    if (n) hipLaunchKernelGGL(copy16_kernel, grid_for(n), dim3(kBlock), 0, st, n, (const float4 *)src, (float4 *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st)
+{
+    const size_t n = bytes / 16;
+    if (n) hipLaunchKernelGGL(zero16_kernel, grid_for(n), dim3(kBlock), 0, st, n, (float4 *)dst);
+    return hipGetLastError();
+}
+
+}  // namespace hrd

@@ -1,0 +1,179 @@
+// Wilson hopping stencil on one parity (the "inner Dirac kernel" of the
+// paper's Sec. 2.1, here covering the whole single-GPU lattice), with fused
+// epilogues for the plain operator D = m - H/2, the off-diagonal blocks
+// D_eo = -H_eo/2 and the second stage of the even/odd operator
+// D^ = m - (1/m) D_eo D_oe.
+//
+// One thread per target site.  For each of the 8 directions the neighbour
+// spinor (opposite parity) is spin-projected to a half spinor with
+// (1 -+ g_mu), multiplied by U or U^+ on colour, and the lower two spin
+// components are reconstructed from the upper two (the projector has rank 2).
+// Every link is read exactly once per hop; the sign s_mu(x) of the
+// time-antiperiodic boundary is applied to the half spinor.
+#include "kernels.h"
+#include "spin.h"
+
+namespace hrd {
+
+namespace {
+
+template <int MU, bool DAG, int REP, typename R>
+__device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, int p, const void *U,
+                                        const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
+{
+    constexpr int N = NCol<REP>::value;
+    constexpr int NC = 4 * N;
+    constexpr int SF = DAG ? +1 : -1;  // forward term uses (1 + SF g_mu)
+    constexpr int SB = -SF;            // backward term uses (1 + SB g_mu)
+    using IO = SpinorIO<R>;
+    using LIO = LinkIO<REP, R>;
+    {
+        const int j = nbr_fwd(g, s, MU);
+        Cx<R> psi[NC];
+        IO::template load<NC>(src, g.Vh, j, psi);
+        const auto l = LIO::load(U, g.Vh, p, MU, idx);
+        Cx<R> h0[N], h1[N], u0[N], u1[N];
+        project<MU, SF, N, R>(psi, h0, h1);
+        if (MU == 0 && s.x[0] == g.L[0] - 1) {
+#pragma unroll
+            for (int c = 0; c < N; c++) {
+                h0[c] = -h0[c];
+                h1[c] = -h1[c];
+            }
+        }
+        link_mul(l, h0, u0);
+        link_mul(l, h1, u1);
+        reconstruct<MU, SF, N, R>(acc, u0, u1);
+    }
+    {
+        const int j = nbr_bwd(g, s, MU);
+        Cx<R> psi[NC];
+        IO::template load<NC>(src, g.Vh, j, psi);
+        const auto l = LIO::load(U, g.Vh, 1 - p, MU, j);
+        Cx<R> h0[N], h1[N], u0[N], u1[N];
+        project<MU, SB, N, R>(psi, h0, h1);
+        if (MU == 0 && s.x[0] == 0) {
+#pragma unroll
+            for (int c = 0; c < N; c++) {
+                h0[c] = -h0[c];
+                h1[c] = -h1[c];
+            }
+        }
+        link_mul_dag(l, h0, u0);
+        link_mul_dag(l, h1, u1);
+        reconstruct<MU, SB, N, R>(acc, u0, u1);
+    }
+}
+
+// out = a psi_self(x) + b (H psi_src)(x) on the target parity; FULL runs both
+// parities in one launch (blocks alternate parity), NORM writes one partial
+// of ||out||^2 per block.
+template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL>
+__global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a)
+{
+    constexpr int N = NCol<REP>::value;
+    constexpr int NC = 4 * N;
+    const Geom &g = a.g;
+    int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int part_idx = lb;
+    int p;
+    const char *src;
+    const char *self;
+    char *dst;
+    if constexpr (FULL) {
+        p = lb & 1;
+        lb >>= 1;
+        src = a.src + (size_t)(1 - p) * a.half_bytes;
+        self = a.src + (size_t)p * a.half_bytes;
+        dst = a.dst + (size_t)p * a.half_bytes;
+    } else {
+        p = a.parity;
+        src = a.src;
+        self = a.self;
+        dst = a.dst;
+    }
+    const int idx = lb * kBlock + threadIdx.x;
+    double nrm = 0;
+    if (idx < g.Vh) {
+        const Site s = eo_site(g, idx, p);
+        Cx<R> acc[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) acc[k] = Cx<R>{0, 0};
+        hop_dir<0, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
+        hop_dir<1, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
+        hop_dir<2, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
+        hop_dir<3, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
+        const R cb = (R)a.b;
+        Cx<R> out[NC];
+        if constexpr (HAS_A) {
+            const R ca = (R)a.a;
+            Cx<R> self_v[NC];
+            SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
+#pragma unroll
+            for (int k = 0; k < NC; k++)
+                out[k] = Cx<R>{ca * self_v[k].re + cb * acc[k].re, ca * self_v[k].im + cb * acc[k].im};
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; k++) out[k] = cb * acc[k];
+        }
+        SpinorIO<R>::template store<NC>(dst, g.Vh, idx, out);
+        if constexpr (NORM) {
+#pragma unroll
+            for (int k = 0; k < NC; k++)
+                nrm += (double)out[k].re * (double)out[k].re + (double)out[k].im * (double)out[k].im;
+        }
+    }
+    if constexpr (NORM) {
+        const double t = block_sum<kBlock>(nrm);
+        if (threadIdx.x == 0) a.partials[part_idx] = t;
+    }
+}
+
+template <int REP, typename R>
+hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
+{
+    const int nb = hop_blocks(a.g) * (full ? 2 : 1);
+    const dim3 grid(nb), block(kBlock);
+#define HRD_LAUNCH(D, A, NR, F) hipLaunchKernelGGL((hop_kernel<REP, R, D, A, NR, F>), grid, block, 0, st, a)
+    if (full) {
+        if (dag)
+            HRD_LAUNCH(true, true, false, true);
+        else
+            HRD_LAUNCH(false, true, false, true);
+    } else if (dag) {
+        if (has_a) {
+            if (norm) HRD_LAUNCH(true, true, true, false);
+            else HRD_LAUNCH(true, true, false, false);
+        } else {
+            if (norm) HRD_LAUNCH(true, false, true, false);
+            else HRD_LAUNCH(true, false, false, false);
+        }
+    } else {
+        if (has_a) {
+            if (norm) HRD_LAUNCH(false, true, true, false);
+            else HRD_LAUNCH(false, true, false, false);
+        } else {
+            if (norm) HRD_LAUNCH(false, false, true, false);
+            else HRD_LAUNCH(false, false, false, false);
+        }
+    }
+#undef HRD_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int hop_blocks(const Geom &g) { return (g.Vh + kBlock - 1) / kBlock; }
+
+hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
+                      hipStream_t st)
+{
+    if (rep == HRD_FUND) {
+        if (prec == HRD_F64) return dispatch_hop<HRD_FUND, double>(a, dag, has_a, norm, full, st);
+        return dispatch_hop<HRD_FUND, float>(a, dag, has_a, norm, full, st);
+    }
+    if (prec == HRD_F64) return dispatch_hop<HRD_ADJ, double>(a, dag, has_a, norm, full, st);
+    return dispatch_hop<HRD_ADJ, float>(a, dag, has_a, norm, full, st);
+}
+
+}  // namespace hrd

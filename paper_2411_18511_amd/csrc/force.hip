@@ -1,0 +1,103 @@
+// Derivative of L = Re<X, D[U] Y> with respect to the links (the fermion
+// force of the HMC that the paper's even/odd operator serves, Sec. 2.1):
+//   G_mu(x) = -1/2 s_mu(x) sum_spin [ X(x) (x) ((1 - g_mu) Y(x+mu))^*
+//                                   + ((1 + g_mu) Y(x)) (x) X(x+mu)^* ].
+// Because (1 + SIG g_mu) is Hermitian, squares to twice itself and has the
+// half-spinor structure of spin.h, each spin sum collapses to two spin
+// components:  sum_s A_s (x) ((1+SIG g)B)_s^* = sum_{t=0,1} h(A)_t (x) h(B)_t^*
+// with h the upper half of (1 + SIG g_mu) applied to the field.
+// One thread per site computes the four links leaving it; every output link
+// has exactly one writer (no atomics).
+#include "kernels.h"
+#include "spin.h"
+
+namespace hrd {
+
+namespace {
+
+template <int MU, int REP>
+__device__ __forceinline__ void force_dir(const Geom &g, const Site &s, int idx, int p, const char *Xb, const char *Yb,
+                                          size_t half, const Cx<double> (&Xx)[4 * NCol<REP>::value],
+                                          const Cx<double> (&Yx)[4 * NCol<REP>::value], void *F, double scale)
+{
+    constexpr int N = NCol<REP>::value;
+    constexpr int NC = 4 * N;
+    const int j = nbr_fwd(g, s, MU);
+    const char *Xn = Xb + (size_t)(1 - p) * half;
+    const char *Yn = Yb + (size_t)(1 - p) * half;
+    Cx<double> Xf[NC], Yf[NC];
+    SpinorIO<double>::template load<NC>(Xn, g.Vh, j, Xf);
+    SpinorIO<double>::template load<NC>(Yn, g.Vh, j, Yf);
+    // first term: (1 - g) projections of X(x) and Y(x+mu)
+    Cx<double> a0[N], a1[N], b0[N], b1[N];
+    project<MU, -1, N, double>(Xx, a0, a1);
+    project<MU, -1, N, double>(Yf, b0, b1);
+    // second term: (1 + g) projections of Y(x) and X(x+mu)
+    Cx<double> c0[N], c1[N], d0[N], d1[N];
+    project<MU, +1, N, double>(Yx, c0, c1);
+    project<MU, +1, N, double>(Xf, d0, d1);
+    const double sg = (MU == 0 && s.x[0] == g.L[0] - 1) ? -1.0 : 1.0;
+    const double w = -0.5 * sg * scale;
+    Cx<double> G[N][N];
+#pragma unroll
+    for (int i = 0; i < N; i++)
+#pragma unroll
+        for (int k = 0; k < N; k++) {
+            // a_i conj(b_k) + ...
+            Cx<double> z = cmulc(b0[k], a0[i]);
+            z = cfmac(b1[k], a1[i], z);
+            z = cfmac(d0[k], c0[i], z);
+            z = cfmac(d1[k], c1[i], z);
+            G[i][k] = Cx<double>{w * z.re, w * z.im};
+        }
+    if constexpr (REP == HRD_FUND) {
+        FundLink<double> l;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) l.u[i][k] = G[i][k];
+        LinkIO<HRD_FUND, double>::store(F, g.Vh, p, MU, idx, l);
+    } else {
+        AdjLink<double> l;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) l.r[i][k] = G[i][k].re;
+        LinkIO<HRD_ADJ, double>::store(F, g.Vh, p, MU, idx, l);
+    }
+}
+
+template <int REP>
+__global__ __launch_bounds__(kBlock) void force_kernel(Geom g, const char *X, const char *Y, void *F, double scale)
+{
+    constexpr int N = NCol<REP>::value;
+    constexpr int NC = 4 * N;
+    int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = lb & 1;
+    lb >>= 1;
+    const int idx = lb * kBlock + threadIdx.x;
+    if (idx >= g.Vh) return;
+    const size_t half = (size_t)g.Vh * NC * sizeof(Cx<double>);
+    const Site s = eo_site(g, idx, p);
+    Cx<double> Xx[NC], Yx[NC];
+    SpinorIO<double>::template load<NC>(X + (size_t)p * half, g.Vh, idx, Xx);
+    SpinorIO<double>::template load<NC>(Y + (size_t)p * half, g.Vh, idx, Yx);
+    force_dir<0, REP>(g, s, idx, p, X, Y, half, Xx, Yx, F, scale);
+    force_dir<1, REP>(g, s, idx, p, X, Y, half, Xx, Yx, F, scale);
+    force_dir<2, REP>(g, s, idx, p, X, Y, half, Xx, Yx, F, scale);
+    force_dir<3, REP>(g, s, idx, p, X, Y, half, Xx, Yx, F, scale);
+}
+
+}  // namespace
+
+hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, void *F, double scale, hipStream_t st)
+{
+    const dim3 grid(2 * hop_blocks(g)), block(kBlock);
+    const char *x = reinterpret_cast<const char *>(X);
+    const char *y = reinterpret_cast<const char *>(Y);
+    if (rep == HRD_FUND) hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale);
+    else hipLaunchKernelGGL(force_kernel<HRD_ADJ>, grid, block, 0, st, g, x, y, F, scale);
+    return hipGetLastError();
+}
+
+}  // namespace hrd

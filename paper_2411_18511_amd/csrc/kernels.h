@@ -1,0 +1,98 @@
+// Internal launch interface between the C ABI / host drivers and the HIP
+// kernels of libhrd.  Nothing here is exported.
+#pragma once
+
+#include "common.h"
+
+namespace hrd {
+
+// ----- hopping stencil (dslash.hip) ---------------------------------------
+struct HopArgs {
+    Geom g;
+    const void *U;      // packed gauge field
+    const char *src;    // source field (opposite parity); FULL: full-lattice psi
+    const char *self;   // HAS_A: target-parity field for the a*psi term
+    char *dst;          // output (target parity); FULL: full-lattice out
+    double a, b;        // out = a * self + b * (H src)
+    double *partials;   // NORM: one ||out||^2 partial per block
+    int parity;         // target parity (ignored by FULL)
+    size_t half_bytes;  // FULL: bytes of one parity block of a spinor
+};
+
+int hop_blocks(const Geom &g);
+hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
+                      hipStream_t st);
+
+// ----- field preparation (pack.hip) ----------------------------------------
+hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,
+                              bool unpack, hipStream_t st);
+hipError_t launch_pack_gauge(int rep, int prec, const Geom &g, const void *nat, void *packed, bool unpack,
+                             hipStream_t st);
+hipError_t launch_represent(int prec_out, const Geom &g, const void *Uf, void *Ua, hipStream_t st);
+hipError_t launch_represent_backward(const Geom &g, const void *Uf, const void *ga, void *Gf, hipStream_t st);
+hipError_t launch_convert_gauge(int rep, const Geom &g, const void *U64, void *U32, hipStream_t st);
+// nparity blocks of Vh sites, ncomp complex components per site
+hipError_t launch_convert_spinor(int Vh, int nparity, int ncomp, bool to_f32, const void *in, void *out,
+                                 hipStream_t st);
+
+// ----- level-1 linear algebra (blas.hip) ------------------------------------
+// All reductions write kRedBlocks partials; finalize_* sums them in a fixed
+// order on one block.
+constexpr int kRedBlocks = 1024;
+
+// Complex-pair view of a packed field: n complex numbers, F64 or F32.
+hipError_t launch_dot_partials(int prec, size_t n, const void *a, const void *b, double *partials,
+                               hipStream_t st);  // 2 partials per block (re, im)
+hipError_t launch_norm_partials(int prec, size_t n, const void *a, double *partials, hipStream_t st);
+hipError_t launch_axpy(int prec, size_t n, double ar, double ai, const void *x, void *y, double *partials,
+                       hipStream_t st);  // partials may be null
+hipError_t launch_xpay(int prec, size_t n, const void *x, double ar, double ai, void *y, hipStream_t st);
+// sums[0..ncol) = column sums of a [nblk][ncol] partial table
+hipError_t launch_finalize(const double *partials, int nblk, int ncol, double *sums, hipStream_t st);
+
+// ----- CG building blocks (blas.hip) -----------------------------------------
+// Device scalar slots used by the CG drivers.
+enum ScalarSlot {
+    S_RR = 0,      // current ||r||^2
+    S_PAP = 1,     // <p, A p> = ||D^ p||^2
+    S_ALPHA = 2,   // rr / pAp
+    S_BETA = 3,    // rr_new / rr
+    S_RRNEW = 4,   // ||r_new||^2
+    S_FLAG = 5,    // breakdown flag (non-zero)
+    S_BB = 6,      // ||b||^2
+    S_RROLD = 7,   // ||r||^2 before the last beta stage
+    S_COUNT = 8
+};
+// Sum partials of ||D^p||^2 and set alpha = rr / pAp (flag breakdown).
+hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st);
+// Sum partials of ||r||^2 into rr_new and set beta = rr_new / rr, rr = rr_new.
+hipError_t launch_cg_beta(const double *partials, int nblk, double *sc, hipStream_t st);
+// r <- r - alpha Ap (F64 or F32 fields), partials of ||r||^2 (FP64).
+hipError_t launch_cg_update_r(int prec, size_t n, void *r, const void *Ap, const double *sc, double *partials,
+                              hipStream_t st);
+// F64 CG: x <- x + alpha p ; p <- r + beta p.
+hipError_t launch_cg_update_xp64(size_t n, void *x, void *p, const void *r, const double *sc, hipStream_t st);
+// Mixed CG: x64 <- x64 + alpha f64(p32) ; p32 <- r32 + beta p32.  ncomp
+// complex components per site, Vh sites (layout conversion inside).
+hipError_t launch_cg_update_xp_mixed(int Vh, int ncomp, void *x64, void *p32, const void *r32,
+                                     const double *sc, hipStream_t st);
+// Mixed CG, reliable-update iteration: x64 <- x64 + alpha f64(p32).
+hipError_t launch_cg_update_x_mixed(int Vh, int ncomp, void *x64, const void *p32, const double *sc, hipStream_t st);
+// p32 <- r32 + beta p32 with beta = rr / rr_old (after a reliable update).
+hipError_t launch_cg_update_p32(size_t n16, void *p32, const void *r32, const double *sc, hipStream_t st);
+// Reliable update: r64 = b - Ax64 ; r32 = f32(r64) ; partials of ||r64||^2.
+hipError_t launch_cg_residual_mixed(int Vh, int ncomp, const void *b, const void *Ax, void *r64, void *r32,
+                                    double *partials, hipStream_t st);
+// r = b - Ax (F64), partials of ||r||^2.
+hipError_t launch_cg_residual64(size_t n, const void *b, const void *Ax, void *r, double *partials,
+                                hipStream_t st);
+// p32 <- r32 (copy) ; used at (re)starts.
+hipError_t launch_copy(size_t bytes, const void *src, void *dst, hipStream_t st);
+// dst = 0
+hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st);
+
+// ----- force (force.hip) ---------------------------------------------------
+hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, void *F, double scale,
+                        hipStream_t st);
+
+}  // namespace hrd

@@ -1,0 +1,454 @@
+"""Python binding of libhrd (ctypes): argument marshalling over the C ABI.
+
+Every function takes and returns torch tensors on the GPU and forwards raw
+device pointers, sizes and torch's current HIP stream to the library; no
+computation happens here.  Packed fields are plain ``torch.uint8`` buffers
+of the byte size the library reports (``spinor_bytes`` / ``gauge_bytes``);
+natural-layout fields are complex128 (spinors [V, 4, N], gauge [4, V, 2, 2])
+or float64 (adjoint gauge [4, V, 3, 3]) tensors, with V = T*L1*L2*L3 in
+lexicographic site order.
+
+The library is loaded from this directory; if it is missing the import
+fails (build it with ``__graft_entry__.build()``): there is no CPU fallback.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libhrd.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"libhrd.so not found at {LIBPATH}; build it with __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIBPATH)
+
+# enums (hrd.h)
+OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
+FUND, ADJ = 0, 1
+F64, F32 = 0, 1
+FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
+SITES_ALL, SITES_EVEN, SITES_ODD = 0, 1, 2
+CG_F64, CG_MIXED = 0, 1
+
+_STATUS_NAMES = {0: "HRD_OK", 1: "HRD_EINVAL", 2: "HRD_ESHAPE", 3: "HRD_EALIAS", 4: "HRD_EHIP",
+                 5: "HRD_ENOCONV", 6: "HRD_EBREAKDOWN", 7: "HRD_ESIZE"}
+_REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, FUND: FUND, ADJ: ADJ}
+_PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, F64: F64, F32: F32,
+          torch.float64: F64, torch.float32: F32}
+_PARITIES = {"full": FULL, "eo": EO, "hop_eo": HOP_EO, "hop_oe": HOP_OE,
+             FULL: FULL, EO: EO, HOP_EO: HOP_EO, HOP_OE: HOP_OE}
+_SITES = {"all": SITES_ALL, "even": SITES_EVEN, "odd": SITES_ODD,
+          SITES_ALL: SITES_ALL, SITES_EVEN: SITES_EVEN, SITES_ODD: SITES_ODD}
+_MODES = {"f64": CG_F64, "fp64": CG_F64, "mixed": CG_MIXED, CG_F64: CG_F64, CG_MIXED: CG_MIXED}
+
+
+class HrdError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("true_rel_residual", ctypes.c_double), ("iterated_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("rep", ctypes.c_int), ("nrhs", ctypes.c_int), ("m0", ctypes.c_double),
+                ("U32", ctypes.c_void_p), ("U64", ctypes.c_void_p), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("sites_per_tile", ctypes.c_int), ("rhs_per_tile", ctypes.c_int),
+                ("block_threads", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+_LP = ctypes.POINTER(Lattice)
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("hrd_last_error", ctypes.c_char_p)
+_sig("hrd_version", ctypes.c_char_p)
+_sig("hrd_spinor_bytes", _S, _LP, _I, _I, _I)
+_sig("hrd_gauge_bytes", _S, _LP, _I, _I)
+_sig("hrd_pack_gauge", _I, _LP, _I, _I, _P, _P, _P)
+_sig("hrd_unpack_gauge", _I, _LP, _I, _I, _P, _P, _P)
+_sig("hrd_represent", _I, _LP, _P, _P, _I, _P)
+_sig("hrd_represent_backward", _I, _LP, _P, _P, _P, _P)
+_sig("hrd_convert_gauge", _I, _LP, _I, _P, _P, _P)
+_sig("hrd_pack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
+_sig("hrd_unpack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
+_sig("hrd_convert_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
+_sig("hrd_dirac_workspace_bytes", _S, _LP, _I, _I, _I)
+_sig("hrd_dirac_apply", _I, _LP, _I, _I, _P, _P, _P, _D, _I, _I, _P, _P)
+_sig("hrd_blas_workspace_bytes", _S)
+_sig("hrd_blas_dot", _I, _LP, _I, _I, _I, _P, _P, ctypes.POINTER(_D), _P, _P)
+_sig("hrd_blas_norm2", _I, _LP, _I, _I, _I, _P, ctypes.POINTER(_D), _P, _P)
+_sig("hrd_blas_axpy", _I, _LP, _I, _I, _I, _D, _D, _P, _P, ctypes.POINTER(_D), _P, _P)
+_sig("hrd_blas_xpay", _I, _LP, _I, _I, _I, _P, _D, _D, _P, _P)
+_sig("hrd_cg_workspace_bytes", _S, _LP, _I, _I)
+_sig("hrd_cg_solve", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _D, _I, _D, _P, _S, ctypes.POINTER(CgInfo), _P)
+_sig("hrd_dirac_force", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _P)
+_sig("hrd_action_force_workspace_bytes", _S, _LP, _I)
+_sig("hrd_action_force", _I, _LP, _I, _P, _P, _P, _D, _D, _P, _S, _P)
+_HAS_BATCHED = hasattr(_lib, "hrd_dirac_apply_batched")
+if _HAS_BATCHED:
+    _sig("hrd_batched_workspace_bytes", _S, ctypes.POINTER(Problem), _I, _I)
+    _sig("hrd_dirac_apply_batched", _I, ctypes.POINTER(Problem), _I, _I, _I, ctypes.POINTER(Tune), _P, _S, _P)
+    _sig("hrd_cg_batched_workspace_bytes", _S, ctypes.POINTER(Problem), _I)
+    _sig("hrd_cg_solve_batched", _I, ctypes.POINTER(Problem), _I, _D, _I, _D, ctypes.POINTER(Tune), _P, _S,
+         ctypes.POINTER(CgInfo), _P)
+    _sig("hrd_autotune_batched", _I, ctypes.POINTER(Problem), _I, _P, _S, ctypes.c_char_p, ctypes.POINTER(Tune),
+         _P)
+
+
+def _check(status, allow=()):
+    if status != OK and status not in allow:
+        raise HrdError(status, _lib.hrd_last_error().decode())
+    return status
+
+
+def version():
+    return _lib.hrd_version().decode()
+
+
+def lattice(dims):
+    dims = tuple(int(d) for d in dims)
+    if len(dims) != 4:
+        raise ValueError("dims must be (T, L1, L2, L3)")
+    return Lattice((ctypes.c_int * 4)(*dims))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, nbytes, what):
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what}: {have} bytes < required {nbytes}")
+
+
+def _empty(nbytes, device=None):
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device or "cuda")
+
+
+def _zeros(nbytes, device=None):
+    return torch.zeros(int(nbytes), dtype=torch.uint8, device=device or "cuda")
+
+
+@dataclass
+class Geometry:
+    dims: tuple
+    rep: int
+
+    @property
+    def volume(self):
+        T, a, b, c = self.dims
+        return T * a * b * c
+
+    @property
+    def ncolour(self):
+        return 2 if self.rep == FUND else 3
+
+
+def spinor_bytes(dims, rep, prec, nparity):
+    return _lib.hrd_spinor_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec], int(nparity))
+
+
+def gauge_bytes(dims, rep, prec):
+    return _lib.hrd_gauge_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec])
+
+
+# ---------------------------------------------------------------------------
+# gauge preparation
+# ---------------------------------------------------------------------------
+
+def pack_gauge(U_nat, dims, rep, prec):
+    rep, prec = _REPS[rep], _PRECS[prec]
+    out = _empty(gauge_bytes(dims, rep, prec), U_nat.device)
+    _check(_lib.hrd_pack_gauge(ctypes.byref(lattice(dims)), rep, prec, _ptr(U_nat), _ptr(out), _stream()))
+    return out
+
+
+def unpack_gauge(U, dims, rep, prec):
+    rep, prec = _REPS[rep], _PRECS[prec]
+    V = Geometry(tuple(dims), rep).volume
+    if rep == FUND:
+        out = torch.empty((4, V, 2, 2), dtype=torch.complex128, device=U.device)
+    else:
+        out = torch.empty((4, V, 3, 3), dtype=torch.float64, device=U.device)
+    _check(_lib.hrd_unpack_gauge(ctypes.byref(lattice(dims)), rep, prec, _ptr(U), _ptr(out), _stream()))
+    return out
+
+
+def represent(U_fund, dims, prec=F64):
+    prec = _PRECS[prec]
+    out = _empty(gauge_bytes(dims, ADJ, prec), U_fund.device)
+    _check(_lib.hrd_represent(ctypes.byref(lattice(dims)), _ptr(U_fund), _ptr(out), prec, _stream()))
+    return out
+
+
+def represent_backward(U_fund, g_adj, dims):
+    out = _empty(gauge_bytes(dims, FUND, F64), U_fund.device)
+    _check(_lib.hrd_represent_backward(ctypes.byref(lattice(dims)), _ptr(U_fund), _ptr(g_adj), _ptr(out), _stream()))
+    return out
+
+
+def convert_gauge(U64, dims, rep):
+    rep = _REPS[rep]
+    out = _empty(gauge_bytes(dims, rep, F32), U64.device)
+    _check(_lib.hrd_convert_gauge(ctypes.byref(lattice(dims)), rep, _ptr(U64), _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# spinors
+# ---------------------------------------------------------------------------
+
+def pack_spinor(psi_nat, dims, rep, prec, sites="all"):
+    rep, prec, sites = _REPS[rep], _PRECS[prec], _SITES[sites]
+    np_ = 2 if sites == SITES_ALL else 1
+    out = _empty(spinor_bytes(dims, rep, prec, np_), psi_nat.device)
+    _check(_lib.hrd_pack_spinor(ctypes.byref(lattice(dims)), rep, prec, sites, _ptr(psi_nat), _ptr(out), _stream()))
+    return out
+
+
+def unpack_spinor(psi, dims, rep, prec, sites="all", out=None):
+    rep, prec, sites = _REPS[rep], _PRECS[prec], _SITES[sites]
+    g = Geometry(tuple(dims), rep)
+    if out is None:
+        out = torch.zeros((g.volume, 4, g.ncolour), dtype=torch.complex128, device=psi.device)
+    _check(_lib.hrd_unpack_spinor(ctypes.byref(lattice(dims)), rep, prec, sites, _ptr(psi), _ptr(out), _stream()))
+    return out
+
+
+def convert_spinor(psi, dims, rep, nparity, to_f32):
+    rep = _REPS[rep]
+    out = _empty(spinor_bytes(dims, rep, F32 if to_f32 else F64, nparity), psi.device)
+    _check(_lib.hrd_convert_spinor(ctypes.byref(lattice(dims)), rep, int(nparity), int(bool(to_f32)), _ptr(psi),
+                                   _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+
+def dirac_workspace_bytes(dims, rep, prec, parity):
+    return _lib.hrd_dirac_workspace_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec],
+                                          _PARITIES[parity])
+
+
+def dirac_apply(U, psi, m0, rep, parity, dims, prec=F64, dagger=False, out=None, work=None):
+    """out = X psi for X in {D, D^, D_eo, D_oe} (parity 'full', 'eo', 'hop_eo', 'hop_oe')."""
+    rep, prec, parity = _REPS[rep], _PRECS[prec], _PARITIES[parity]
+    np_ = 2 if parity == FULL else 1
+    nbytes = spinor_bytes(dims, rep, prec, np_)
+    _need(psi, nbytes, "psi")
+    _need(U, gauge_bytes(dims, rep, prec), "U")
+    if out is None:
+        out = _empty(nbytes, psi.device)
+    wb = dirac_workspace_bytes(dims, rep, prec, parity)
+    if wb and work is None:
+        work = _empty(wb, psi.device)
+    _check(_lib.hrd_dirac_apply(ctypes.byref(lattice(dims)), rep, prec, _ptr(U), _ptr(psi), _ptr(out), float(m0),
+                                parity, int(bool(dagger)), _ptr(work) if wb else None, _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# level-1 linear algebra
+# ---------------------------------------------------------------------------
+
+_blas_work = {}
+
+
+def _blas_ws(device):
+    key = str(device)
+    if key not in _blas_work:
+        _blas_work[key] = _empty(_lib.hrd_blas_workspace_bytes(), device)
+    return _blas_work[key]
+
+
+def blas_dot(a, b, dims, rep, prec, nparity):
+    res = (ctypes.c_double * 2)()
+    _check(_lib.hrd_blas_dot(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec], int(nparity), _ptr(a), _ptr(b),
+                             res, _ptr(_blas_ws(a.device)), _stream()))
+    return complex(res[0], res[1])
+
+
+def blas_norm2(a, dims, rep, prec, nparity):
+    res = ctypes.c_double()
+    _check(_lib.hrd_blas_norm2(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec], int(nparity), _ptr(a),
+                               ctypes.byref(res), _ptr(_blas_ws(a.device)), _stream()))
+    return res.value
+
+
+def blas_axpy(a, x, y, dims, rep, prec, nparity, norm=False):
+    a = complex(a)
+    res = ctypes.c_double()
+    _check(_lib.hrd_blas_axpy(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec], int(nparity), a.real, a.imag,
+                              _ptr(x), _ptr(y), ctypes.byref(res) if norm else None, _ptr(_blas_ws(x.device)),
+                              _stream()))
+    return res.value if norm else None
+
+
+def blas_xpay(x, a, y, dims, rep, prec, nparity):
+    a = complex(a)
+    _check(_lib.hrd_blas_xpay(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec], int(nparity), _ptr(x), a.real,
+                              a.imag, _ptr(y), _stream()))
+
+
+# ---------------------------------------------------------------------------
+# solvers
+# ---------------------------------------------------------------------------
+
+def cg_workspace_bytes(dims, rep, mode):
+    return _lib.hrd_cg_workspace_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _MODES[mode])
+
+
+def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=10000, delta=0.1, work=None,
+             allow_noconv=False):
+    """Solve (D^+ D^) x = b on even sites; returns (x, info dict)."""
+    rep, mode = _REPS[rep], _MODES[mode]
+    nb = spinor_bytes(dims, rep, F64, 1)
+    _need(b, nb, "b")
+    x = _zeros(nb, b.device) if x0 is None else x0.clone()
+    wb = cg_workspace_bytes(dims, rep, mode)
+    if work is None:
+        work = _empty(wb, b.device)
+    info = CgInfo()
+    st = _lib.hrd_cg_solve(ctypes.byref(lattice(dims)), rep, mode, _ptr(U64), _ptr(U32), _ptr(b), _ptr(x), float(m0),
+                           float(tol), int(maxiter), float(delta), _ptr(work), wb, ctypes.byref(info), _stream())
+    _check(st, allow=(ENOCONV,) if allow_noconv else ())
+    d = info.as_dict()
+    d["status"] = _STATUS_NAMES[st]
+    return x, d
+
+
+# ---------------------------------------------------------------------------
+# force
+# ---------------------------------------------------------------------------
+
+def dirac_force(U, X, Y, dims, rep, scale=1.0, prec=F64):
+    """F = scale * d/dU Re<X, D[U] Y> (packed FP64 gauge layout)."""
+    rep = _REPS[rep]
+    out = _empty(gauge_bytes(dims, rep, F64), X.device)
+    _check(_lib.hrd_dirac_force(ctypes.byref(lattice(dims)), rep, _PRECS[prec], _ptr(U), _ptr(X), _ptr(Y), _ptr(out),
+                                float(scale), _stream()))
+    return out
+
+
+def action_force(U, xi, m0, dims, rep, scale=1.0):
+    """scale * dS/dU for S = phi^+ (D^+ D^)^{-1} phi, given xi = (D^+ D^)^{-1} phi."""
+    rep = _REPS[rep]
+    out = _empty(gauge_bytes(dims, rep, F64), xi.device)
+    wb = _lib.hrd_action_force_workspace_bytes(ctypes.byref(lattice(dims)), rep)
+    work = _empty(wb, xi.device)
+    _check(_lib.hrd_action_force(ctypes.byref(lattice(dims)), rep, _ptr(U), _ptr(xi), _ptr(out), float(m0),
+                                 float(scale), _ptr(work), wb, _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+
+def has_batched():
+    return _HAS_BATCHED
+
+
+def make_problems(specs):
+    """specs: list of dicts with dims, rep, nrhs, m0, U32, U64, src, dst (tensors or None)."""
+    arr = (Problem * len(specs))()
+    for i, s in enumerate(specs):
+        arr[i].lat = lattice(s["dims"])
+        arr[i].rep = _REPS[s["rep"]]
+        arr[i].nrhs = int(s["nrhs"])
+        arr[i].m0 = float(s["m0"])
+        arr[i].U32 = s["U32"].data_ptr() if s.get("U32") is not None else None
+        arr[i].U64 = s["U64"].data_ptr() if s.get("U64") is not None else None
+        arr[i].src = s["src"].data_ptr() if s.get("src") is not None else None
+        arr[i].dst = s["dst"].data_ptr() if s.get("dst") is not None else None
+    return arr
+
+
+def _tune_ptr(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        t = Tune(**tune)
+    else:
+        t = tune
+    return ctypes.byref(t)
+
+
+def batched_workspace_bytes(problems, parity):
+    return _lib.hrd_batched_workspace_bytes(problems, len(problems), _PARITIES[parity])
+
+
+def dirac_apply_batched(problems, parity, dagger=False, tune=None, work=None, device="cuda"):
+    wb = batched_workspace_bytes(problems, parity)
+    if work is None:
+        work = _empty(max(wb, 1), device)
+    _check(_lib.hrd_dirac_apply_batched(problems, len(problems), _PARITIES[parity], int(bool(dagger)),
+                                        _tune_ptr(tune), _ptr(work), wb, _stream()))
+
+
+def cg_solve_batched(problems, tol, maxiter=10000, delta=0.1, tune=None, work=None, device="cuda",
+                     allow_noconv=False):
+    wb = _lib.hrd_cg_batched_workspace_bytes(problems, len(problems))
+    if work is None:
+        work = _empty(wb, device)
+    ntot = sum(p.nrhs for p in problems)
+    infos = (CgInfo * ntot)()
+    st = _lib.hrd_cg_solve_batched(problems, len(problems), float(tol), int(maxiter), float(delta), _tune_ptr(tune),
+                                   _ptr(work), wb, infos, _stream())
+    _check(st, allow=(ENOCONV,) if allow_noconv else ())
+    return [i.as_dict() for i in infos], _STATUS_NAMES[st]
+
+
+def autotune_batched(problems, cache_path=None, work=None, device="cuda"):
+    wb = batched_workspace_bytes(problems, EO)
+    if work is None:
+        work = _empty(wb, device)
+    best = Tune()
+    _check(_lib.hrd_autotune_batched(problems, len(problems), _ptr(work), wb,
+                                     cache_path.encode() if cache_path else None, ctypes.byref(best), _stream()))
+    return best.as_dict()

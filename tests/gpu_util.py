@@ -1,0 +1,77 @@
+"""Helpers for the GPU parity tests: move seeded numpy fields to the GPU in the
+natural layout, run the library through its binding, bring results back.
+
+The oracle and the library both consume the arrays produced by
+``paper_2411_18511_amd.inputs``; nothing here computes any part of the method.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2411_18511_amd import inputs
+
+requires_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")
+
+
+def hrd():
+    from paper_2411_18511_amd import hrd as _h
+
+    return _h
+
+
+def to_dev_spinor(psi):
+    """numpy [T, L1, L2, L3, 4, N] -> cuda complex128 [V, 4, N]."""
+    V = int(np.prod(psi.shape[:4]))
+    return torch.from_numpy(np.ascontiguousarray(psi.reshape(V, 4, psi.shape[-1]))).cuda()
+
+
+def from_dev_spinor(t, dims):
+    n = t.shape[-1]
+    return t.cpu().numpy().reshape(tuple(dims) + (4, n))
+
+
+def to_dev_gauge(U):
+    """numpy [4, T, L1, L2, L3, N, N] -> cuda [4, V, N, N] (complex128 or float64)."""
+    V = int(np.prod(U.shape[1:5]))
+    return torch.from_numpy(np.ascontiguousarray(U.reshape(4, V, U.shape[-2], U.shape[-1]))).cuda()
+
+
+def from_dev_gauge(t, dims):
+    return t.cpu().numpy().reshape((4,) + tuple(dims) + tuple(t.shape[-2:]))
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+class Field:
+    """A seeded problem: fundamental links, optional adjoint links, packed on the GPU."""
+
+    def __init__(self, dims, rep, seed, kind="haar"):
+        import oracle as O
+
+        h = hrd()
+        self.dims = tuple(dims)
+        self.rep = rep
+        self.n = 2 if rep == "fund" else 3
+        self.Uf = inputs.gauge_field(dims, seed, kind=kind)
+        self.Uf_dev = to_dev_gauge(self.Uf)
+        Uf64 = h.pack_gauge(self.Uf_dev, dims, "fund", "f64")
+        if rep == "fund":
+            self.U_orc = self.Uf
+            self.U64 = Uf64
+        else:
+            self.U_orc = O.represent_adjoint(self.Uf).astype(np.complex128)
+            self.U64 = h.represent(Uf64, dims, "f64")
+        self.Uf64 = Uf64
+        self.U32 = h.convert_gauge(self.U64, dims, rep)
+
+    def spinor(self, seed):
+        return inputs.gaussian_spinor(self.dims, self.n, seed)
+
+    def pack(self, psi, prec="f64", sites="all"):
+        return hrd().pack_spinor(to_dev_spinor(psi), self.dims, self.rep, prec, sites)
+
+    def unpack(self, packed, prec="f64", sites="all"):
+        out = hrd().unpack_spinor(packed, self.dims, self.rep, prec, sites)
+        return from_dev_spinor(out, self.dims)
