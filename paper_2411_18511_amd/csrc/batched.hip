@@ -1,0 +1,901 @@
+// Batched multi-right-hand-side / mixed-volume execution.  The paper advises
+// local volumes of at least 16^4 for SU(2) (Sec. 3); small lattices and many
+// right-hand sides are gathered here into single persistent launches:
+//
+// * a tile is (problem, block of sites, group of G right-hand sides); a
+//   thread owns one site of the tile, loads each of its 8 links once and
+//   applies it to the G spinors of the group, so the gauge field is read once
+//   per site for the whole group;
+// * one persistent grid per hopping stage covers every problem (mixed
+//   volumes and representations): each XCD walks its own contiguous range of
+//   tiles, and the tiles of one site block are adjacent, so the links of a
+//   site block are re-read from that XCD's L2 by the next group;
+// * per-problem geometry comes from a descriptor table in device memory.
+//
+// The batched CG runs one independent mixed-precision reliable-update CG per
+// right-hand side (FP32 operator stages batched, per-RHS FP64 scalars and
+// reductions, FP64 residual recomputation), masking converged systems.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_util.h"
+#include "spin.h"
+
+namespace hrd {
+
+namespace {
+
+constexpr int kMaxProb = 64;
+constexpr int kMaxRhs = 64;
+constexpr int kNumBuf = 6;
+constexpr int kVecBlocks = 64;  // x-blocks per right-hand side in vector kernels
+
+struct BatchDesc {
+    Geom g;
+    int rep;
+    int nrhs;
+    int rhs_base;   // global index of the problem's first right-hand side
+    int tile_base;  // first tile of this problem
+    int ntiles;
+    int nsb;        // site blocks
+    int ngroups;    // right-hand-side groups
+    double m;       // 4 + m0
+    const void *U32;
+    size_t fbytes;  // bytes of one FP32 half field
+    char *buf[kNumBuf];
+};
+
+// Per right-hand side view for the vector stages of the batched CG.
+struct RhsDesc {
+    int Vh, ncomp, nsb, pad;
+    size_t n16;  // 16-byte elements of one FP32 half field
+    char *x64, *r32, *p32, *Ap32;
+};
+
+enum BatchMode { M_NORMAL = 0, M_RELIABLE = 1, M_DONE = 2 };
+
+template <int MU, bool DAG, int REP, int G>
+__device__ __forceinline__ void hop_dir_multi(const Geom &g, const Site &s, int idx, int p, const void *U,
+                                              const char *src, size_t fbytes, const bool (&act)[G],
+                                              Cx<float> (&acc)[G][4 * NCol<REP>::value])
+{
+    constexpr int N = NCol<REP>::value;
+    constexpr int NC = 4 * N;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    using IO = SpinorIO<float>;
+    using LIO = LinkIO<REP, float>;
+    {
+        const int j = nbr_fwd(g, s, MU);
+        const auto l = LIO::template load<true>(U, g.Vh, p, MU, idx);
+        const bool neg = (MU == 0 && s.x[0] == g.L[0] - 1);
+#pragma unroll
+        for (int k = 0; k < G; k++) {
+            if (!act[k]) continue;
+            Cx<float> psi[NC];
+            IO::template load<NC>(src + (size_t)k * fbytes, g.Vh, j, psi);
+            Cx<float> h0[N], h1[N], u0[N], u1[N];
+            project<MU, SF, N, float>(psi, h0, h1);
+            if (neg) {
+#pragma unroll
+                for (int c = 0; c < N; c++) {
+                    h0[c] = -h0[c];
+                    h1[c] = -h1[c];
+                }
+            }
+            link_mul(l, h0, u0);
+            link_mul(l, h1, u1);
+            reconstruct<MU, SF, N, float>(acc[k], u0, u1);
+        }
+    }
+    {
+        const int j = nbr_bwd(g, s, MU);
+        const auto l = LIO::template load<true>(U, g.Vh, 1 - p, MU, j);
+        const bool neg = (MU == 0 && s.x[0] == 0);
+#pragma unroll
+        for (int k = 0; k < G; k++) {
+            if (!act[k]) continue;
+            Cx<float> psi[NC];
+            IO::template load<NC>(src + (size_t)k * fbytes, g.Vh, j, psi);
+            Cx<float> h0[N], h1[N], u0[N], u1[N];
+            project<MU, SB, N, float>(psi, h0, h1);
+            if (neg) {
+#pragma unroll
+                for (int c = 0; c < N; c++) {
+                    h0[c] = -h0[c];
+                    h1[c] = -h1[c];
+                }
+            }
+            link_mul_dag(l, h0, u0);
+            link_mul_dag(l, h1, u1);
+            reconstruct<MU, SB, N, float>(acc[k], u0, u1);
+        }
+    }
+}
+
+// One tile: sites [sb * blockDim, +blockDim) of the target parity, right-hand
+// sides [grp * G, +G) of the problem.  EPI2: out = m self + acc / (2m), plus
+// per-right-hand-side ||out||^2 partials when `partials` is not NULL; else
+// out = -acc / 2.
+template <int REP, int G, bool DAG, bool EPI2>
+__device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp, int parity, int src_id, int self_id,
+                                             int dst_id, const int *mode, double *partials, int part_stride)
+{
+    constexpr int NC = 4 * NCol<REP>::value;
+    const Geom &g = d.g;
+    const int r0 = grp * G;
+    bool act[G];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+        act[k] = (r0 + k < d.nrhs) && (!mode || mode[d.rhs_base + r0 + k] != M_DONE);
+        any = any || act[k];
+    }
+    if (!any) return;  // uniform across the block
+    const int w = sb * (int)blockDim.x + (int)threadIdx.x;
+    const bool in = w < g.Vh;
+    Cx<float> acc[G][NC];
+#pragma unroll
+    for (int k = 0; k < G; k++)
+#pragma unroll
+        for (int c = 0; c < NC; c++) acc[k][c] = Cx<float>{0.f, 0.f};
+    int idx = 0;
+    const char *src = d.buf[src_id] + (size_t)r0 * d.fbytes;
+    if (in) {
+        const Site s = slab_site(g, w, parity, &idx);
+        hop_dir_multi<0, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
+        hop_dir_multi<1, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
+        hop_dir_multi<2, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
+        hop_dir_multi<3, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
+    }
+    const float ca = (float)d.m, cb = EPI2 ? (float)(0.5 / d.m) : -0.5f;
+#pragma unroll
+    for (int k = 0; k < G; k++) {
+        if (!act[k]) continue;
+        double nrm = 0;
+        if (in) {
+            Cx<float> out[NC];
+            if constexpr (EPI2) {
+                Cx<float> sv[NC];
+                SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)(r0 + k) * d.fbytes, g.Vh, idx, sv);
+#pragma unroll
+                for (int c = 0; c < NC; c++)
+                    out[c] = Cx<float>{ca * sv[c].re + cb * acc[k][c].re, ca * sv[c].im + cb * acc[k][c].im};
+#pragma unroll
+                for (int c = 0; c < NC; c++) nrm += (double)out[c].re * out[c].re + (double)out[c].im * out[c].im;
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; c++) out[c] = cb * acc[k][c];
+            }
+            SpinorIO<float>::template store<NC, true>(d.buf[dst_id] + (size_t)(r0 + k) * d.fbytes, g.Vh, idx, out);
+        }
+        if (EPI2 && partials != nullptr) {
+            // block-wide sum of ||out||^2, only when the caller wants it (a
+            // uniform kernel argument); every thread of the block reaches it
+            // since act[k] is uniform
+            __shared__ double part[16];
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nrm;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0;
+                for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) t += part[wv];
+                partials[(size_t)(d.rhs_base + r0 + k) * part_stride + sb] = t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int G, bool DAG, bool EPI2>
+__global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs, int nprob, int ntiles, int parity,
+                                                          int src_id, int self_id, int dst_id, const int *mode,
+                                                          double *partials, int part_stride)
+{
+    // each XCD walks its own contiguous range of tiles (gridDim.x is a multiple of 8)
+    const int xcd = blockIdx.x % kNumXcd;
+    const int slot = blockIdx.x / kNumXcd;
+    const int per = gridDim.x / kNumXcd;
+    const int t0 = (int)((long)ntiles * xcd / kNumXcd);
+    const int t1 = (int)((long)ntiles * (xcd + 1) / kNumXcd);
+    int p = 0;
+    for (int tile = t0 + slot; tile < t1; tile += per) {
+        while (p + 1 < nprob && tile >= descs[p + 1].tile_base) p++;
+        while (tile < descs[p].tile_base) p--;
+        const BatchDesc &d = descs[p];
+        const int local = tile - d.tile_base;
+        const int sb = local / d.ngroups;
+        const int grp = local - sb * d.ngroups;
+        if (d.rep == HRD_FUND)
+            batched_tile<HRD_FUND, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+        else
+            batched_tile<HRD_ADJ, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+    }
+}
+
+// ----- per right-hand-side vector stages of the batched CG -----------------
+
+__device__ __forceinline__ double blk_sum256(double v)
+{
+    __shared__ double part[4];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) s = part[0] + part[1] + part[2] + part[3];
+    __syncthreads();
+    return s;
+}
+
+// r <- r - alpha Ap ; partials of ||r||^2 (grid: kVecBlocks x nrhs)
+__global__ __launch_bounds__(256) void bcg_update_r_kernel(const RhsDesc *rd, const int *mode, const double *sc,
+                                                           double *partials)
+{
+    const int r = blockIdx.y;
+    if (mode[r] == M_DONE) return;
+    const RhsDesc d = rd[r];
+    const float alpha = (float)sc[r * S_COUNT + S_ALPHA];
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.n16; i += (size_t)gridDim.x * 256) {
+        float4 *R = reinterpret_cast<float4 *>(d.r32) + i;
+        const float4 a = reinterpret_cast<const float4 *>(d.Ap32)[i];
+        float4 v = *R;
+        v.x -= alpha * a.x;
+        v.y -= alpha * a.y;
+        v.z -= alpha * a.z;
+        v.w -= alpha * a.w;
+        *R = v;
+        s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+    }
+    s = blk_sum256(s);
+    if (threadIdx.x == 0) partials[(size_t)r * kVecBlocks + blockIdx.x] = s;
+}
+
+// x64 += alpha f64(p32) ; p32 = r32 + beta p32 for mode == M_NORMAL;
+// only the x update for mode == M_RELIABLE when only_x is set.
+__global__ __launch_bounds__(256) void bcg_update_xp_kernel(const RhsDesc *rd, const int *mode, const double *sc,
+                                                            int only_x)
+{
+    const int r = blockIdx.y;
+    const int md = mode[r];
+    if (only_x ? md != M_RELIABLE : md != M_NORMAL) return;
+    const RhsDesc d = rd[r];
+    const double alpha = sc[r * S_COUNT + S_ALPHA];
+    const float beta = (float)sc[r * S_COUNT + S_BETA];
+    const int npl = d.ncomp / 2;
+    const long n = (long)npl * d.Vh;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) {
+        const int q = (int)(t / d.Vh);
+        const int j = (int)(t - (long)q * d.Vh);
+        float4 *P = reinterpret_cast<float4 *>(d.p32) + t;
+        const float4 pv = *P;
+        double2 *X = reinterpret_cast<double2 *>(d.x64);
+        const size_t i0 = (size_t)(2 * q) * d.Vh + j, i1 = i0 + d.Vh;
+        double2 x0 = X[i0], x1 = X[i1];
+        x0.x += alpha * (double)pv.x;
+        x0.y += alpha * (double)pv.y;
+        x1.x += alpha * (double)pv.z;
+        x1.y += alpha * (double)pv.w;
+        X[i0] = x0;
+        X[i1] = x1;
+        if (!only_x) {
+            const float4 rv = reinterpret_cast<const float4 *>(d.r32)[t];
+            *P = make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+        }
+    }
+}
+
+// Per right-hand side: alpha = rr / pAp from the hop partials (count nsb).
+__global__ __launch_bounds__(256) void bcg_alpha_kernel(const RhsDesc *rd, const int *mode, const double *partials,
+                                                        int part_stride, double *sc)
+{
+    const int r = blockIdx.x;
+    if (mode[r] == M_DONE) return;
+    const int n = rd[r].nsb;
+    double s = 0;
+    for (int k = threadIdx.x; k < n; k += 256) s += partials[(size_t)r * part_stride + k];
+    s = blk_sum256(s);
+    if (threadIdx.x == 0) {
+        double *c = sc + r * S_COUNT;
+        c[S_PAP] = s;
+        if (!(s > 0.0) || !isfinite(s)) {
+            c[S_FLAG] = 1.0;
+            c[S_ALPHA] = 0.0;
+        } else {
+            c[S_ALPHA] = c[S_RR] / s;
+        }
+    }
+}
+
+// Per right-hand side: rr_new from the update partials, beta = rr_new / rr.
+__global__ __launch_bounds__(256) void bcg_beta_kernel(const int *mode, const double *partials, double *sc)
+{
+    const int r = blockIdx.x;
+    if (mode[r] == M_DONE) return;
+    double s = 0;
+    for (int k = threadIdx.x; k < kVecBlocks; k += 256) s += partials[(size_t)r * kVecBlocks + k];
+    s = blk_sum256(s);
+    if (threadIdx.x == 0) {
+        double *c = sc + r * S_COUNT;
+        c[S_RRNEW] = s;
+        if (!isfinite(s)) {
+            c[S_FLAG] = 2.0;
+            c[S_BETA] = 0.0;
+        } else {
+            c[S_BETA] = c[S_RR] > 0.0 ? s / c[S_RR] : 0.0;
+        }
+        c[S_RROLD] = c[S_RR];
+        c[S_RR] = s;
+    }
+}
+
+// ----- host side ------------------------------------------------------------
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((char *)b) {}
+    void *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        void *p = base ? base + off : nullptr;
+        off += n;
+        return p;
+    }
+    size_t used() const { return (off + 255) & ~(size_t)255; }
+};
+
+hrd_status check_problems(const hrd_problem *probs, int nprob, bool need_u64)
+{
+    if (!probs || nprob < 1 || nprob > kMaxProb) return fail(HRD_EINVAL, "nprob must be in 1..%d", kMaxProb);
+    int total = 0;
+    for (int i = 0; i < nprob; i++) {
+        const hrd_problem &p = probs[i];
+        HRD_TRY(check_lattice(&p.lat));
+        HRD_TRY(check_rep_prec(p.rep, HRD_F32));
+        if (p.nrhs < 1 || p.nrhs > kMaxRhs) return fail(HRD_EINVAL, "problem %d: nrhs must be in 1..%d", i, kMaxRhs);
+        if (!p.U32 || !p.src || !p.dst) return fail(HRD_EINVAL, "problem %d: NULL pointer", i);
+        if (need_u64 && !p.U64) return fail(HRD_EINVAL, "problem %d: the batched CG needs U64", i);
+        if (!std::isfinite(p.m0) || 4.0 + p.m0 == 0.0) return fail(HRD_EINVAL, "problem %d: invalid m0", i);
+        total += p.nrhs;
+    }
+    if (total > kMaxProb * 4) return fail(HRD_EINVAL, "too many right-hand sides in total (%d)", total);
+    return HRD_OK;
+}
+
+hrd_tune resolve_tune(const hrd_tune *t)
+{
+    hrd_tune r{128, 4, 128, 4};
+    if (t) {
+        if (t->sites_per_tile > 0) r.sites_per_tile = t->sites_per_tile;
+        if (t->rhs_per_tile > 0) r.rhs_per_tile = t->rhs_per_tile;
+        if (t->block_threads > 0) r.block_threads = t->block_threads;
+        if (t->blocks_per_cu > 0) r.blocks_per_cu = t->blocks_per_cu;
+    }
+    r.block_threads = r.sites_per_tile;  // one thread per site of a tile
+    return r;
+}
+
+hrd_status check_tune(const hrd_tune &t)
+{
+    if (t.sites_per_tile != 64 && t.sites_per_tile != 128 && t.sites_per_tile != 256)
+        return fail(HRD_EINVAL, "sites_per_tile must be 64, 128 or 256");
+    if (t.rhs_per_tile != 1 && t.rhs_per_tile != 2 && t.rhs_per_tile != 3 && t.rhs_per_tile != 4 && t.rhs_per_tile != 6)
+        return fail(HRD_EINVAL, "rhs_per_tile must be 1, 2, 3, 4 or 6");
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return fail(HRD_EINVAL, "blocks_per_cu must be in 1..16");
+    return HRD_OK;
+}
+
+// Fill the descriptor table; returns total tiles.
+int build_descs(const hrd_problem *probs, int nprob, const hrd_tune &t, std::vector<BatchDesc> &d, int *max_nsb)
+{
+    d.assign(nprob, BatchDesc{});
+    int tiles = 0, rhs = 0;
+    *max_nsb = 0;
+    for (int i = 0; i < nprob; i++) {
+        BatchDesc &b = d[i];
+        b.g = make_geom(probs[i].lat.dims);
+        b.rep = probs[i].rep;
+        b.nrhs = probs[i].nrhs;
+        b.rhs_base = rhs;
+        b.nsb = (b.g.Vh + t.sites_per_tile - 1) / t.sites_per_tile;
+        b.ngroups = (b.nrhs + t.rhs_per_tile - 1) / t.rhs_per_tile;
+        b.ntiles = b.nsb * b.ngroups;
+        b.tile_base = tiles;
+        b.m = 4.0 + probs[i].m0;
+        b.U32 = probs[i].U32;
+        b.fbytes = spinor_bytes(&probs[i].lat, b.rep, HRD_F32, 1);
+        tiles += b.ntiles;
+        rhs += b.nrhs;
+        *max_nsb = std::max(*max_nsb, b.nsb);
+    }
+    return tiles;
+}
+
+template <int G, bool DAG, bool EPI2>
+void launch_g(int grid, int block, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity, int s,
+              int self, int dst, const int *mode, double *parts, int ps)
+{
+    hipLaunchKernelGGL((batched_hop_kernel<G, DAG, EPI2>), dim3(grid), dim3(block), 0, st, dd, nprob, ntiles, parity,
+                       s, self, dst, mode, parts, ps);
+}
+
+template <bool DAG, bool EPI2>
+hipError_t launch_stage_t(const hrd_tune &t, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity,
+                          int s, int self, int dst, const int *mode, double *parts, int ps)
+{
+    int grid = kNumCu * t.blocks_per_cu;
+    grid = (grid / kNumXcd) * kNumXcd;
+    const int blk = t.sites_per_tile;
+    switch (t.rhs_per_tile) {
+        case 1: launch_g<1, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
+        case 2: launch_g<2, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
+        case 3: launch_g<3, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
+        case 4: launch_g<4, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
+        default: launch_g<6, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const hrd_tune &t, bool dag, bool epi2, hipStream_t st, const BatchDesc *dd, int nprob,
+                        int ntiles, int parity, int s, int self, int dst, const int *mode, double *parts, int ps)
+{
+    if (dag) {
+        if (epi2) return launch_stage_t<true, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+        return launch_stage_t<true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+    }
+    if (epi2) return launch_stage_t<false, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+    return launch_stage_t<false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+}
+
+// Workspace of the batched apply: descriptor table, then one FP32 odd
+// temporary per right-hand side (HRD_EO).
+size_t apply_ws(const hrd_problem *probs, int nprob, hrd_parity parity, BatchDesc **dd, char ***tmp, void *work)
+{
+    Carve c(work);
+    *dd = (BatchDesc *)c.take(sizeof(BatchDesc) * kMaxProb);
+    static thread_local char *tmps[kMaxProb];
+    for (int i = 0; i < nprob; i++) {
+        const size_t fb = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F32, 1);
+        tmps[i] = parity == HRD_EO ? (char *)c.take(fb * probs[i].nrhs) : nullptr;
+    }
+    if (tmp) *tmp = tmps;
+    return c.used();
+}
+
+// Runs the batched hopping stages of `parity` over the prepared table.
+hrd_status run_batched(const std::vector<BatchDesc> &hd, BatchDesc *dd, int ntiles, const hrd_tune &t,
+                       hrd_parity parity, bool dag, hipStream_t st)
+{
+    const int np = (int)hd.size();
+    HRD_TRY(check_hip(hipMemcpyAsync(dd, hd.data(), sizeof(BatchDesc) * np, hipMemcpyHostToDevice, st), "desc upload"));
+    hipError_t e;
+    if (parity == HRD_EO) {
+        // buffers: 0 src, 1 dst, 2 tmp
+        e = launch_stage(t, dag, false, st, dd, np, ntiles, 1, 0, 0, 2, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = launch_stage(t, dag, true, st, dd, np, ntiles, 0, 2, 0, 1, nullptr, nullptr, 0);
+    } else {
+        const int target = parity == HRD_HOP_EO ? 0 : 1;
+        e = launch_stage(t, dag, false, st, dd, np, ntiles, target, 0, 0, 1, nullptr, nullptr, 0);
+    }
+    return check_hip(e, "batched hop launch");
+}
+
+}  // namespace
+
+}  // namespace hrd
+
+using namespace hrd;
+
+extern "C" {
+
+size_t hrd_batched_workspace_bytes(const hrd_problem *probs, int nprob, hrd_parity parity)
+{
+    if (check_problems(probs, nprob, false) != HRD_OK) return 0;
+    BatchDesc *dd;
+    return apply_ws(probs, nprob, parity, &dd, nullptr, nullptr);
+}
+
+hrd_status hrd_dirac_apply_batched(const hrd_problem *probs, int nprob, hrd_parity parity, int dagger,
+                                   const hrd_tune *tune, void *work, size_t work_bytes, void *stream)
+{
+    HRD_TRY(check_problems(probs, nprob, false));
+    if (parity != HRD_EO && parity != HRD_HOP_EO && parity != HRD_HOP_OE)
+        return fail(HRD_EINVAL, "batched parity must be HRD_EO, HRD_HOP_EO or HRD_HOP_OE");
+    const hrd_tune t = resolve_tune(tune);
+    HRD_TRY(check_tune(t));
+    if (!work) return fail(HRD_EINVAL, "NULL workspace");
+    BatchDesc *dd;
+    char **tmps;
+    const size_t need = apply_ws(probs, nprob, parity, &dd, &tmps, work);
+    if (work_bytes < need) return fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need);
+    for (int i = 0; i < nprob; i++) {
+        const size_t fb = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F32, 1) * probs[i].nrhs;
+        for (int j = 0; j < nprob; j++) {
+            const size_t fbj = spinor_bytes(&probs[j].lat, probs[j].rep, HRD_F32, 1) * probs[j].nrhs;
+            if (overlap(probs[i].dst, fb, probs[j].src, fbj)) return fail(HRD_EALIAS, "problem %d dst overlaps a source", i);
+            if (j != i && overlap(probs[i].dst, fb, probs[j].dst, fbj)) return fail(HRD_EALIAS, "destinations overlap");
+        }
+        if (overlap(work, need, probs[i].dst, fb) || overlap(work, need, probs[i].src, fb))
+            return fail(HRD_EALIAS, "workspace overlaps problem %d", i);
+    }
+    std::vector<BatchDesc> hd;
+    int max_nsb;
+    const int ntiles = build_descs(probs, nprob, t, hd, &max_nsb);
+    for (int i = 0; i < nprob; i++) {
+        hd[i].buf[0] = (char *)probs[i].src;
+        hd[i].buf[1] = (char *)probs[i].dst;
+        hd[i].buf[2] = tmps[i];
+    }
+    return run_batched(hd, dd, ntiles, t, parity, dagger != 0, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched mixed-precision CG
+// ---------------------------------------------------------------------------
+
+namespace hrd {
+namespace {
+
+struct BcgWork {
+    BatchDesc *dd;
+    RhsDesc *rd;
+    int *mode;
+    double *sc, *parts, *vparts;
+    // FP64 temporaries sized for the largest problem (reliable updates)
+    void *q64, *Ap64, *t64, *r64;
+    // per problem FP32 buffers (nrhs fields each): p, t (odd), q, Ap, r
+    char *f32[kMaxProb][5];
+};
+
+size_t bcg_carve(const hrd_problem *probs, int nprob, void *work, BcgWork *w)
+{
+    Carve c(work);
+    BcgWork t{};
+    int total = 0;
+    size_t max64 = 0;
+    int max_nsb = 0;
+    for (int i = 0; i < nprob; i++) {
+        total += probs[i].nrhs;
+        max64 = std::max(max64, spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1));
+        const Geom g = make_geom(probs[i].lat.dims);
+        max_nsb = std::max(max_nsb, (g.Vh + 63) / 64);
+    }
+    t.dd = (BatchDesc *)c.take(sizeof(BatchDesc) * kMaxProb);
+    t.rd = (RhsDesc *)c.take(sizeof(RhsDesc) * total);
+    t.mode = (int *)c.take(sizeof(int) * total);
+    t.sc = (double *)c.take(sizeof(double) * S_COUNT * total);
+    t.parts = (double *)c.take(sizeof(double) * (size_t)std::max(max_nsb, kRedBlocks) * total);
+    t.vparts = (double *)c.take(sizeof(double) * kVecBlocks * total);
+    t.q64 = c.take(max64);
+    t.Ap64 = c.take(max64);
+    t.t64 = c.take(max64);
+    t.r64 = c.take(max64);
+    for (int i = 0; i < nprob; i++) {
+        const size_t fb = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F32, 1) * probs[i].nrhs;
+        for (int k = 0; k < 5; k++) t.f32[i][k] = (char *)c.take(fb);
+    }
+    if (w) *w = t;
+    return c.used();
+}
+
+}  // namespace
+}  // namespace hrd
+
+extern "C" {
+
+size_t hrd_cg_batched_workspace_bytes(const hrd_problem *probs, int nprob)
+{
+    if (check_problems(probs, nprob, true) != HRD_OK) return 0;
+    return bcg_carve(probs, nprob, nullptr, nullptr);
+}
+
+hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol, int maxiter, double delta,
+                                const hrd_tune *tune, void *work, size_t work_bytes, hrd_cg_info *infos, void *stream)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    HRD_TRY(check_problems(probs, nprob, true));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HRD_EINVAL, "tol must be positive");
+    if (maxiter < 0) return fail(HRD_EINVAL, "maxiter must be >= 0");
+    if (!work) return fail(HRD_EINVAL, "NULL workspace");
+    hrd_tune t = resolve_tune(tune);
+    HRD_TRY(check_tune(t));
+    if (delta <= 0.0) delta = 0.1;
+    const size_t need = bcg_carve(probs, nprob, nullptr, nullptr);
+    if (work_bytes < need) return fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need);
+    for (int i = 0; i < nprob; i++) {
+        const size_t fb = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1) * probs[i].nrhs;
+        if (overlap(probs[i].dst, fb, probs[i].src, fb)) return fail(HRD_EALIAS, "problem %d: x overlaps b", i);
+        if (overlap(work, need, probs[i].dst, fb) || overlap(work, need, probs[i].src, fb))
+            return fail(HRD_EALIAS, "workspace overlaps problem %d", i);
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    BcgWork w;
+    bcg_carve(probs, nprob, work, &w);
+
+    std::vector<BatchDesc> hd;
+    int max_nsb;
+    const int ntiles = build_descs(probs, nprob, t, hd, &max_nsb);
+    const int part_stride = std::max(max_nsb, kRedBlocks);
+    for (int i = 0; i < nprob; i++)
+        for (int k = 0; k < 5; k++) hd[i].buf[k] = w.f32[i][k];
+    enum { B_P = 0, B_T = 1, B_Q = 2, B_AP = 3, B_R = 4 };
+    int total = 0;
+    for (int i = 0; i < nprob; i++) total += probs[i].nrhs;
+    std::vector<RhsDesc> rdh(total);
+    std::vector<int> prob_of(total), slot_of(total);
+    for (int i = 0, r = 0; i < nprob; i++)
+        for (int k = 0; k < probs[i].nrhs; k++, r++) {
+            const Geom &g = hd[i].g;
+            RhsDesc &d = rdh[r];
+            d.Vh = g.Vh;
+            d.ncomp = ncomp_of(probs[i].rep);
+            d.nsb = hd[i].nsb;
+            d.n16 = hd[i].fbytes / 16;
+            d.x64 = (char *)probs[i].dst + (size_t)k * spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1);
+            d.r32 = w.f32[i][B_R] + (size_t)k * hd[i].fbytes;
+            d.p32 = w.f32[i][B_P] + (size_t)k * hd[i].fbytes;
+            d.Ap32 = w.f32[i][B_AP] + (size_t)k * hd[i].fbytes;
+            prob_of[r] = i;
+            slot_of[r] = k;
+        }
+    std::vector<int> mode(total, M_NORMAL);
+    std::vector<double> sc((size_t)S_COUNT * total);
+    std::vector<double> bnorm(total), rmax(total);
+    std::vector<hrd_cg_info> inf(total);
+    std::vector<hrd_status> stat(total, HRD_OK);
+
+#define BT(expr, what) HRD_TRY(check_hip((expr), what))
+    BT(hipMemcpyAsync(w.dd, hd.data(), sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, st), "desc upload");
+    BT(hipMemcpyAsync(w.rd, rdh.data(), sizeof(RhsDesc) * total, hipMemcpyHostToDevice, st), "rhs upload");
+    BT(launch_zero(sizeof(double) * S_COUNT * total, w.sc, st), "zero");
+
+    auto b64_of = [&](int r) {
+        const int i = prob_of[r];
+        return (const char *)probs[i].src + (size_t)slot_of[r] * spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1);
+    };
+    // FP64 residual of one right-hand side: r64 = b - A x ; r32 = f32(r64) ; sc[S_RR] = ||r64||^2
+    auto residual = [&](int r) -> hrd_status {
+        const int i = prob_of[r];
+        const Geom &g = hd[i].g;
+        const int rep = probs[i].rep;
+        const double m0 = probs[i].m0;
+        hipError_t e = apply_dhat(rep, HRD_F64, g, probs[i].U64, rdh[r].x64, w.q64, w.t64, m0, false, nullptr, st);
+        if (e == hipSuccess) e = apply_dhat(rep, HRD_F64, g, probs[i].U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st);
+        if (e == hipSuccess)
+            e = launch_cg_residual_mixed(g.Vh, ncomp_of(rep), b64_of(r), w.Ap64, w.r64, rdh[r].r32, w.parts, st);
+        if (e == hipSuccess) e = launch_finalize(w.parts, kRedBlocks, 1, w.sc + (size_t)r * S_COUNT + S_RR, st);
+        return check_hip(e, "batched residual");
+    };
+    auto read_sc = [&]() -> hrd_status {
+        HRD_TRY(check_hip(hipMemcpyAsync(sc.data(), w.sc, sizeof(double) * S_COUNT * total, hipMemcpyDeviceToHost, st),
+                          "scalars"));
+        return check_hip(hipStreamSynchronize(st), "sync");
+    };
+    auto upload_mode = [&]() {
+        return check_hip(hipMemcpyAsync(w.mode, mode.data(), sizeof(int) * total, hipMemcpyHostToDevice, st), "mode");
+    };
+
+    // ||b||^2 and initial residuals
+    for (int r = 0; r < total; r++) {
+        const int i = prob_of[r];
+        const size_t n16 = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1) / 16;
+        BT(launch_norm_partials(HRD_F64, n16, b64_of(r), w.parts, st), "norm b");
+        BT(launch_finalize(w.parts, kRedBlocks, 1, w.sc + (size_t)r * S_COUNT + S_BB, st), "finalize");
+        HRD_TRY(residual(r));
+    }
+    HRD_TRY(read_sc());
+    int active = 0;
+    for (int r = 0; r < total; r++) {
+        const double bb = sc[(size_t)r * S_COUNT + S_BB];
+        const double rr = sc[(size_t)r * S_COUNT + S_RR];
+        bnorm[r] = std::sqrt(bb);
+        if (!std::isfinite(bb) || !std::isfinite(rr)) {
+            stat[r] = HRD_EBREAKDOWN;
+            mode[r] = M_DONE;
+            continue;
+        }
+        inf[r].true_rel_residual = bb > 0 ? std::sqrt(rr) / bnorm[r] : 0.0;
+        inf[r].iterated_rel_residual = inf[r].true_rel_residual;
+        if (bb == 0.0 || std::sqrt(rr) <= tol * bnorm[r]) {
+            mode[r] = M_DONE;
+            if (bb == 0.0) BT(launch_zero(spinor_bytes(&probs[prob_of[r]].lat, probs[prob_of[r]].rep, HRD_F64, 1),
+                                          rdh[r].x64, st), "zero x");
+            continue;
+        }
+        rmax[r] = std::sqrt(rr);
+        BT(launch_copy(hd[prob_of[r]].fbytes, rdh[r].r32, rdh[r].p32, st), "p = r");
+        active++;
+    }
+    HRD_TRY(upload_mode());
+
+    const dim3 vgrid(kVecBlocks, total);
+    int it = 0;
+    while (active > 0 && it < maxiter) {
+        it++;
+        // q = D^ p (norm partials), alpha; Ap = D^+ q
+        BT(launch_stage(t, false, false, st, w.dd, nprob, ntiles, 1, B_P, B_P, B_T, w.mode, nullptr, 0), "hop");
+        BT(launch_stage(t, false, true, st, w.dd, nprob, ntiles, 0, B_T, B_P, B_Q, w.mode, w.parts, part_stride), "hop");
+        hipLaunchKernelGGL(bcg_alpha_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc);
+        BT(hipGetLastError(), "alpha");
+        BT(launch_stage(t, true, false, st, w.dd, nprob, ntiles, 1, B_Q, B_Q, B_T, w.mode, nullptr, 0), "hop");
+        BT(launch_stage(t, true, true, st, w.dd, nprob, ntiles, 0, B_T, B_Q, B_AP, w.mode, w.parts, part_stride), "hop");
+        hipLaunchKernelGGL(bcg_update_r_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, w.vparts);
+        BT(hipGetLastError(), "update r");
+        hipLaunchKernelGGL(bcg_beta_kernel, dim3(total), dim3(256), 0, st, w.mode, w.vparts, w.sc);
+        BT(hipGetLastError(), "beta");
+        HRD_TRY(read_sc());
+        std::vector<int> reliable;
+        for (int r = 0; r < total; r++) {
+            if (mode[r] == M_DONE) continue;
+            inf[r].iters++;
+            const double *c = &sc[(size_t)r * S_COUNT];
+            if (c[S_FLAG] != 0.0) {
+                stat[r] = HRD_EBREAKDOWN;
+                mode[r] = M_DONE;
+                active--;
+                continue;
+            }
+            const double rn = std::sqrt(c[S_RR]);
+            inf[r].iterated_rel_residual = rn / bnorm[r];
+            rmax[r] = std::max(rmax[r], rn);
+            if (rn < delta * rmax[r] || rn <= tol * bnorm[r]) {
+                mode[r] = M_RELIABLE;
+                reliable.push_back(r);
+            }
+        }
+        HRD_TRY(upload_mode());
+        hipLaunchKernelGGL(bcg_update_xp_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, 0);
+        BT(hipGetLastError(), "update xp");
+        if (!reliable.empty()) {
+            hipLaunchKernelGGL(bcg_update_xp_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, 1);
+            BT(hipGetLastError(), "update x");
+            for (int r : reliable) HRD_TRY(residual(r));
+            HRD_TRY(read_sc());
+            for (int r : reliable) {
+                inf[r].reliable_updates++;
+                const double rt = std::sqrt(sc[(size_t)r * S_COUNT + S_RR]);
+                inf[r].true_rel_residual = rt / bnorm[r];
+                if (!std::isfinite(rt)) {
+                    stat[r] = HRD_EBREAKDOWN;
+                    mode[r] = M_DONE;
+                    active--;
+                } else if (rt <= tol * bnorm[r]) {
+                    mode[r] = M_DONE;
+                    active--;
+                } else {
+                    rmax[r] = rt;
+                    mode[r] = M_NORMAL;
+                    BT(launch_cg_update_p32(rdh[r].n16, rdh[r].p32, rdh[r].r32, w.sc + (size_t)r * S_COUNT, st), "p");
+                }
+            }
+            HRD_TRY(upload_mode());
+        }
+    }
+    hrd_status result = HRD_OK;
+    for (int r = 0; r < total; r++) {
+        if (mode[r] != M_DONE && stat[r] == HRD_OK) {
+            HRD_TRY(residual(r));
+            stat[r] = HRD_ENOCONV;
+        }
+    }
+    HRD_TRY(read_sc());
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int r = 0; r < total; r++) {
+        if (stat[r] == HRD_ENOCONV) inf[r].true_rel_residual = std::sqrt(sc[(size_t)r * S_COUNT + S_RR]) / bnorm[r];
+        inf[r].seconds = secs;
+        if (infos) infos[r] = inf[r];
+        if (stat[r] == HRD_EBREAKDOWN) result = HRD_EBREAKDOWN;
+        else if (stat[r] == HRD_ENOCONV && result == HRD_OK) result = HRD_ENOCONV;
+    }
+    if (result == HRD_EBREAKDOWN) return fail(HRD_EBREAKDOWN, "breakdown in at least one right-hand side");
+    if (result == HRD_ENOCONV) return fail(HRD_ENOCONV, "at least one right-hand side did not reach tol in %d iterations", maxiter);
+    return HRD_OK;
+#undef BT
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+
+static std::string tune_key(const hrd_problem *probs, int nprob)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = arch + "|batched_hop_f32";
+    char buf[128];
+    for (int i = 0; i < nprob; i++) {
+        snprintf(buf, sizeof(buf), "|%dx%dx%dx%d/%s/%d", probs[i].lat.dims[0], probs[i].lat.dims[1], probs[i].lat.dims[2],
+                 probs[i].lat.dims[3], probs[i].rep == HRD_FUND ? "fund" : "adj", probs[i].nrhs);
+        k += buf;
+    }
+    return k;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, hrd_tune *out)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof(line), f)) {
+        if (strstr(line, pat.c_str())) {
+            hrd_tune t{};
+            const char *p = strstr(line, "\"tune\": [");
+            if (p && sscanf(p, "\"tune\": [%d, %d, %d, %d]", &t.sites_per_tile, &t.rhs_per_tile, &t.block_threads,
+                            &t.blocks_per_cu) == 4) {
+                *out = t;
+                found = true;
+            }
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+extern "C" hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, void *work, size_t work_bytes,
+                                const char *cache_path, hrd_tune *best, void *stream)
+{
+    HRD_TRY(check_problems(probs, nprob, false));
+    if (!best) return fail(HRD_EINVAL, "NULL result");
+    const std::string key = tune_key(probs, nprob);
+    if (cache_path && cache_lookup(cache_path, key, best)) return HRD_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HRD_TRY(check_hip(hipEventCreate(&e0), "event"));
+    HRD_TRY(check_hip(hipEventCreate(&e1), "event"));
+    const int sites[] = {64, 128, 256};
+    const int groups[] = {1, 2, 3, 4, 6};
+    const int bpc[] = {2, 4, 8};
+    float best_ms = 1e30f;
+    hrd_tune bt{};
+    for (int s : sites)
+        for (int gsz : groups)
+            for (int b : bpc) {
+                const hrd_tune cand{s, gsz, s, b};
+                hrd_status rc = hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream);
+                if (rc != HRD_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                float times[5];
+                for (int rep = 0; rep < 5; rep++) {
+                    (void)hipEventRecord(e0, st);
+                    hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    (void)hipEventElapsedTime(&times[rep], e0, e1);
+                }
+                std::sort(times, times + 5);
+                const float med = times[2];
+                // ties (within 1%) go to the smaller tile
+                if (med < best_ms * 0.99f) {
+                    best_ms = med;
+                    bt = cand;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best = bt;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"tune\": [%d, %d, %d, %d], \"median_ms\": %.6f}\n", key.c_str(),
+                    bt.sites_per_tile, bt.rhs_per_tile, bt.block_threads, bt.blocks_per_cu, best_ms);
+            fclose(f);
+        }
+    }
+    return HRD_OK;
+}

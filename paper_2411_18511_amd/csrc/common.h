@@ -53,10 +53,18 @@ struct Geom {
     int L[4];       // {T, L1, L2, L3}
     int stride[4];  // lex strides {L1 L2 L3, L2 L3, L3, 1}
     int Vh;         // sites per parity
+    int R;          // sites per parity in one (t, x1) row: L2 L3 / 2
+    int B;          // x1-slab width of the traversal (divides L1)
     FastDiv div3, div2, div1;
+    FastDiv divR, divB, divT;
 };
 
-inline Geom make_geom(const int dims[4])
+// Slab width for the traversal of the hopping kernels: the lattice is swept
+// in t inside x1-slabs of width B, so the t-neighbour rows of a sweep are
+// B rows apart and stay in the XCD's L2.  B = L1 is plain lexicographic order.
+int choose_slab(const int dims[4]);
+
+inline Geom make_geom(const int dims[4], int slab = 0)
 {
     Geom g;
     for (int i = 0; i < 4; i++) g.L[i] = dims[i];
@@ -68,6 +76,11 @@ inline Geom make_geom(const int dims[4])
     g.div3 = make_fastdiv(dims[3]);
     g.div2 = make_fastdiv(dims[2]);
     g.div1 = make_fastdiv(dims[1]);
+    g.R = dims[2] * dims[3] / 2;
+    g.B = (slab > 0 && dims[1] % slab == 0) ? slab : choose_slab(dims);
+    g.divR = make_fastdiv(g.R);
+    g.divB = make_fastdiv(g.B);
+    g.divT = make_fastdiv(dims[0]);
     return g;
 }
 
@@ -91,6 +104,32 @@ __device__ __forceinline__ Site eo_site(const Geom &g, int idx, int p)
     const int odd = (s.x[0] + s.x[1] + s.x[2] + p) & 1;
     s.x[3] = x3e + odd;
     s.lex = (int)c + odd;
+    return s;
+}
+
+// Site of traversal position w (0 <= w < Vh) in the parity-p block, in slab
+// order: w = ((s T + t) B + x1_in) R + k with x1 = s B + x1_in and k the
+// position inside the (t, x1) row.  Rows are contiguous in the eo index, so
+// consecutive w stay coalesced; *idx receives the eo index.
+__device__ __forceinline__ Site slab_site(const Geom &g, int w, int p, int *idx)
+{
+    Site s;
+    const uint32_t rr = fdiv((uint32_t)w, g.divR);
+    const int k = w - (int)rr * g.R;
+    const uint32_t q = fdiv(rr, g.divB);
+    const int x1_in = (int)(rr - q * (uint32_t)g.B);
+    const uint32_t sl = fdiv(q, g.divT);
+    s.x[0] = (int)(q - sl * (uint32_t)g.L[0]);
+    s.x[1] = (int)sl * g.B + x1_in;
+    const uint32_t c = 2u * (uint32_t)k;
+    const uint32_t x2 = fdiv(c, g.div3);
+    s.x[2] = (int)x2;
+    const int x3e = (int)(c - x2 * (uint32_t)g.L[3]);
+    const int odd = (s.x[0] + s.x[1] + s.x[2] + p) & 1;
+    s.x[3] = x3e + odd;
+    const int row = s.x[0] * g.L[1] + s.x[1];
+    *idx = row * g.R + k;
+    s.lex = 2 * (*idx) + odd;
     return s;
 }
 
@@ -121,6 +160,38 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb)
     const int q = nb / kNumXcd;
     const int r = nb % kNumXcd;
     return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+// ---------------------------------------------------------------------------
+// 16-byte loads and stores, optionally non-temporal (streamed data that is
+// used once: links in a hop, outputs)
+// ---------------------------------------------------------------------------
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ vd2 ld16d(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vd2 *>(p));
+    else return *reinterpret_cast<const vd2 *>(p);
+}
+template <bool NT>
+__device__ __forceinline__ vf4 ld16f(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(p));
+    else return *reinterpret_cast<const vf4 *>(p);
+}
+template <bool NT>
+__device__ __forceinline__ void st16d(void *p, vd2 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vd2 *>(p));
+    else *reinterpret_cast<vd2 *>(p) = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st16f(void *p, vf4 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vf4 *>(p));
+    else *reinterpret_cast<vf4 *>(p) = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -178,45 +249,45 @@ struct SpinorIO;
 
 template <>
 struct SpinorIO<double> {
-    template <int NC>
+    template <int NC, bool NT = false>
     __device__ __forceinline__ static void load(const void *base, int Vh, int site, Cx<double> (&c)[NC])
     {
-        const double2 *p = reinterpret_cast<const double2 *>(base);
+        const char *p = reinterpret_cast<const char *>(base);
 #pragma unroll
         for (int k = 0; k < NC; k++) {
-            const double2 v = p[(size_t)k * Vh + site];
+            const vd2 v = ld16d<NT>(p + ((size_t)k * Vh + site) * 16);
             c[k] = Cx<double>{v.x, v.y};
         }
     }
-    template <int NC>
+    template <int NC, bool NT = false>
     __device__ __forceinline__ static void store(void *base, int Vh, int site, const Cx<double> (&c)[NC])
     {
-        double2 *p = reinterpret_cast<double2 *>(base);
+        char *p = reinterpret_cast<char *>(base);
 #pragma unroll
-        for (int k = 0; k < NC; k++) p[(size_t)k * Vh + site] = make_double2(c[k].re, c[k].im);
+        for (int k = 0; k < NC; k++) st16d<NT>(p + ((size_t)k * Vh + site) * 16, vd2{c[k].re, c[k].im});
     }
 };
 
 template <>
 struct SpinorIO<float> {
-    template <int NC>
+    template <int NC, bool NT = false>
     __device__ __forceinline__ static void load(const void *base, int Vh, int site, Cx<float> (&c)[NC])
     {
-        const float4 *p = reinterpret_cast<const float4 *>(base);
+        const char *p = reinterpret_cast<const char *>(base);
 #pragma unroll
         for (int k = 0; k < NC / 2; k++) {
-            const float4 v = p[(size_t)k * Vh + site];
+            const vf4 v = ld16f<NT>(p + ((size_t)k * Vh + site) * 16);
             c[2 * k] = Cx<float>{v.x, v.y};
             c[2 * k + 1] = Cx<float>{v.z, v.w};
         }
     }
-    template <int NC>
+    template <int NC, bool NT = false>
     __device__ __forceinline__ static void store(void *base, int Vh, int site, const Cx<float> (&c)[NC])
     {
-        float4 *p = reinterpret_cast<float4 *>(base);
+        char *p = reinterpret_cast<char *>(base);
 #pragma unroll
         for (int k = 0; k < NC / 2; k++)
-            p[(size_t)k * Vh + site] = make_float4(c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im);
+            st16f<NT>(p + ((size_t)k * Vh + site) * 16, vf4{c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im});
     }
 };
 
@@ -249,36 +320,38 @@ __host__ __device__ constexpr int spinor_site_bytes(int rep, int prec)
 template <>
 struct LinkIO<HRD_FUND, double> {
     using Link = FundLink<double>;
+    template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
-        const double2 *b = reinterpret_cast<const double2 *>(U) + (size_t)(4 * p + mu) * Vh * 4;
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 64;
         Link l;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const double2 v = b[(size_t)e * Vh + site];
+            const vd2 v = ld16d<NT>(b + ((size_t)e * Vh + site) * 16);
             l.u[e >> 1][e & 1] = Cx<double>{v.x, v.y};
         }
         return l;
     }
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
-        double2 *b = reinterpret_cast<double2 *>(U) + (size_t)(4 * p + mu) * Vh * 4;
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 64;
 #pragma unroll
         for (int e = 0; e < 4; e++)
-            b[(size_t)e * Vh + site] = make_double2(l.u[e >> 1][e & 1].re, l.u[e >> 1][e & 1].im);
+            st16d<false>(b + ((size_t)e * Vh + site) * 16, vd2{l.u[e >> 1][e & 1].re, l.u[e >> 1][e & 1].im});
     }
 };
 
 template <>
 struct LinkIO<HRD_FUND, float> {
     using Link = FundLink<float>;
+    template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
-        const float4 *b = reinterpret_cast<const float4 *>(U) + (size_t)(4 * p + mu) * Vh * 2;
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
         Link l;
 #pragma unroll
         for (int r = 0; r < 2; r++) {
-            const float4 v = b[(size_t)r * Vh + site];
+            const vf4 v = ld16f<NT>(b + ((size_t)r * Vh + site) * 16);
             l.u[r][0] = Cx<float>{v.x, v.y};
             l.u[r][1] = Cx<float>{v.z, v.w};
         }
@@ -286,29 +359,30 @@ struct LinkIO<HRD_FUND, float> {
     }
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
-        float4 *b = reinterpret_cast<float4 *>(U) + (size_t)(4 * p + mu) * Vh * 2;
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
 #pragma unroll
         for (int r = 0; r < 2; r++)
-            b[(size_t)r * Vh + site] = make_float4(l.u[r][0].re, l.u[r][0].im, l.u[r][1].re, l.u[r][1].im);
+            st16f<false>(b + ((size_t)r * Vh + site) * 16, vf4{l.u[r][0].re, l.u[r][0].im, l.u[r][1].re, l.u[r][1].im});
     }
 };
 
 template <>
 struct LinkIO<HRD_ADJ, double> {
     using Link = AdjLink<double>;
+    template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 72;
-        const double2 *b2 = reinterpret_cast<const double2 *>(blk);
         const double *b1 = reinterpret_cast<const double *>(blk + (size_t)Vh * 64);
         double e[9];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const double2 v = b2[(size_t)k * Vh + site];
+            const vd2 v = ld16d<NT>(blk + ((size_t)k * Vh + site) * 16);
             e[2 * k] = v.x;
             e[2 * k + 1] = v.y;
         }
-        e[8] = b1[site];
+        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1 + site);
+        else e[8] = b1[site];
         Link l;
 #pragma unroll
         for (int k = 0; k < 9; k++) l.r[k / 3][k % 3] = e[k];
@@ -317,33 +391,35 @@ struct LinkIO<HRD_ADJ, double> {
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
         char *blk = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 72;
-        double2 *b2 = reinterpret_cast<double2 *>(blk);
         double *b1 = reinterpret_cast<double *>(blk + (size_t)Vh * 64);
+        double e[9];
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            b2[(size_t)k * Vh + site] = make_double2(l.r[(2 * k) / 3][(2 * k) % 3], l.r[(2 * k + 1) / 3][(2 * k + 1) % 3]);
-        b1[site] = l.r[2][2];
+        for (int k = 0; k < 9; k++) e[k] = l.r[k / 3][k % 3];
+#pragma unroll
+        for (int k = 0; k < 4; k++) st16d<false>(blk + ((size_t)k * Vh + site) * 16, vd2{e[2 * k], e[2 * k + 1]});
+        b1[site] = e[8];
     }
 };
 
 template <>
 struct LinkIO<HRD_ADJ, float> {
     using Link = AdjLink<float>;
+    template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 36;
-        const float4 *b4 = reinterpret_cast<const float4 *>(blk);
         const float *b1 = reinterpret_cast<const float *>(blk + (size_t)Vh * 32);
         float e[9];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-            const float4 v = b4[(size_t)k * Vh + site];
+            const vf4 v = ld16f<NT>(blk + ((size_t)k * Vh + site) * 16);
             e[4 * k] = v.x;
             e[4 * k + 1] = v.y;
             e[4 * k + 2] = v.z;
             e[4 * k + 3] = v.w;
         }
-        e[8] = b1[site];
+        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1 + site);
+        else e[8] = b1[site];
         Link l;
 #pragma unroll
         for (int k = 0; k < 9; k++) l.r[k / 3][k % 3] = e[k];
@@ -352,14 +428,13 @@ struct LinkIO<HRD_ADJ, float> {
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
         char *blk = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 36;
-        float4 *b4 = reinterpret_cast<float4 *>(blk);
         float *b1 = reinterpret_cast<float *>(blk + (size_t)Vh * 32);
         float e[9];
 #pragma unroll
         for (int k = 0; k < 9; k++) e[k] = l.r[k / 3][k % 3];
 #pragma unroll
         for (int k = 0; k < 2; k++)
-            b4[(size_t)k * Vh + site] = make_float4(e[4 * k], e[4 * k + 1], e[4 * k + 2], e[4 * k + 3]);
+            st16f<false>(blk + ((size_t)k * Vh + site) * 16, vf4{e[4 * k], e[4 * k + 1], e[4 * k + 2], e[4 * k + 3]});
         b1[site] = e[8];
     }
 };

@@ -13,7 +13,38 @@
 #include "kernels.h"
 #include "spin.h"
 
+// Launch-shape and cache-policy choices of the hopping kernel (measured on
+// MI355X; see the design notes): non-temporal link loads and output stores,
+// minimum waves per SIMD, and the x1-slab width of the traversal (0: chosen
+// per lattice by choose_slab).
+#ifndef HRD_NT_LINKS
+#define HRD_NT_LINKS 1
+#endif
+#ifndef HRD_NT_STORE
+#define HRD_NT_STORE 1
+#endif
+#ifndef HRD_HOP_WAVES
+#define HRD_HOP_WAVES 1
+#endif
+#ifndef HRD_SLAB
+#define HRD_SLAB 0
+#endif
+
 namespace hrd {
+
+// Widest x1-slab whose t-slice holds at most kSlabSites = 6 * 48 * 48 / 2
+// sites per parity (the best of the widths measured on 48^4, where one FP64
+// source slice is then 0.9 MB and the t-1, t, t+1 slices stay in a 4 MB L2).
+int choose_slab(const int dims[4])
+{
+    if (HRD_SLAB > 0 && dims[1] % HRD_SLAB == 0) return HRD_SLAB;
+    constexpr long kSlabSites = 6912;
+    const long R = (long)dims[2] * dims[3] / 2;
+    int best = 1;
+    for (int b = 1; b <= dims[1]; b++)
+        if (dims[1] % b == 0 && (long)b * R <= kSlabSites) best = b;
+    return best;
+}
 
 namespace {
 
@@ -31,7 +62,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         const int j = nbr_fwd(g, s, MU);
         Cx<R> psi[NC];
         IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::load(U, g.Vh, p, MU, idx);
+        const auto l = LIO::template load<HRD_NT_LINKS>(U, g.Vh, p, MU, idx);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SF, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == g.L[0] - 1) {
@@ -49,7 +80,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         const int j = nbr_bwd(g, s, MU);
         Cx<R> psi[NC];
         IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::load(U, g.Vh, 1 - p, MU, j);
+        const auto l = LIO::template load<HRD_NT_LINKS>(U, g.Vh, 1 - p, MU, j);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SB, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == 0) {
@@ -69,7 +100,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 // parities in one launch (blocks alternate parity), NORM writes one partial
 // of ||out||^2 per block.
 template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL>
-__global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
 {
     constexpr int N = NCol<REP>::value;
     constexpr int NC = 4 * N;
@@ -92,10 +123,11 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a)
         self = a.self;
         dst = a.dst;
     }
-    const int idx = lb * kBlock + threadIdx.x;
+    const int w = lb * kBlock + threadIdx.x;
     double nrm = 0;
-    if (idx < g.Vh) {
-        const Site s = eo_site(g, idx, p);
+    if (w < g.Vh) {
+        int idx;
+        const Site s = slab_site(g, w, p, &idx);
         Cx<R> acc[NC];
 #pragma unroll
         for (int k = 0; k < NC; k++) acc[k] = Cx<R>{0, 0};
@@ -116,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs a)
 #pragma unroll
             for (int k = 0; k < NC; k++) out[k] = cb * acc[k];
         }
-        SpinorIO<R>::template store<NC>(dst, g.Vh, idx, out);
+        SpinorIO<R>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
         if constexpr (NORM) {
 #pragma unroll
             for (int k = 0; k < NC; k++)

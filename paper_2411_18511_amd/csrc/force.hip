@@ -75,10 +75,11 @@ __global__ __launch_bounds__(kBlock) void force_kernel(Geom g, const char *X, co
     int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int p = lb & 1;
     lb >>= 1;
-    const int idx = lb * kBlock + threadIdx.x;
-    if (idx >= g.Vh) return;
+    const int w = lb * kBlock + threadIdx.x;
+    if (w >= g.Vh) return;
     const size_t half = (size_t)g.Vh * NC * sizeof(Cx<double>);
-    const Site s = eo_site(g, idx, p);
+    int idx;
+    const Site s = slab_site(g, w, p, &idx);
     Cx<double> Xx[NC], Yx[NC];
     SpinorIO<double>::template load<NC>(X + (size_t)p * half, g.Vh, idx, Xx);
     SpinorIO<double>::template load<NC>(Y + (size_t)p * half, g.Vh, idx, Yx);

@@ -292,6 +292,38 @@ def dirac_apply(U, psi, m0, rep, parity, dims, prec=F64, dagger=False, out=None,
     return out
 
 
+class DiracOp:
+    """A prepared ``dirac_apply``: arguments are marshalled once, so repeated
+    applications cost one foreign call each (used for timing loops and solvers
+    written on top of the library).  The stream is torch's current stream at
+    construction."""
+
+    def __init__(self, U, dims, rep, prec, m0, parity, dagger=False):
+        self.rep, self.prec, self.parity = _REPS[rep], _PRECS[prec], _PARITIES[parity]
+        self.dims = tuple(dims)
+        _need(U, gauge_bytes(dims, self.rep, self.prec), "U")
+        self._U = U
+        self._lat = lattice(dims)
+        self._lat_ref = ctypes.byref(self._lat)
+        np_ = 2 if self.parity == FULL else 1
+        self.field_bytes = spinor_bytes(dims, self.rep, self.prec, np_)
+        wb = dirac_workspace_bytes(dims, self.rep, self.prec, self.parity)
+        self._work = _empty(wb, U.device) if wb else None
+        self._wptr = self._work.data_ptr() if wb else None
+        self._m0 = float(m0)
+        self._dag = int(bool(dagger))
+        self._stream = torch.cuda.current_stream().cuda_stream
+
+    def __call__(self, src, dst):
+        _need(src, self.field_bytes, "src")
+        _need(dst, self.field_bytes, "dst")
+        st = _lib.hrd_dirac_apply(self._lat_ref, self.rep, self.prec, self._U.data_ptr(), src.data_ptr(),
+                                  dst.data_ptr(), self._m0, self.parity, self._dag, self._wptr, self._stream)
+        if st != OK:
+            _check(st)
+        return dst
+
+
 # ---------------------------------------------------------------------------
 # level-1 linear algebra
 # ---------------------------------------------------------------------------

@@ -6,7 +6,8 @@ Tolerances (norm-wise relative, ||y_gpu - y_orc|| / ||y_orc||): 1e-13 in FP64,
 1e-6 in FP32 where the oracle runs on the original FP64 inputs (FP32 input
 rounding ~6e-8 per entry plus ~8-term sums).  Lattices span several 256-site
 tiles with ragged tails and asymmetric extents; 2^4 is the degenerate case
-where forward and backward neighbours coincide.
+where forward and backward neighbours coincide; 4x24x48x48 is swept in x1-slabs
+narrower than L1 (the traversal used at 48^4).
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from gpu_util import Field, from_dev_gauge, requires_gpu, rel_err, hrd
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 TOL = {"f64": 1e-13, "f32": 1e-6}
-LATTICES = [(8, 8, 8, 8), (6, 4, 6, 10), (2, 2, 2, 2), (4, 2, 2, 6)]
+LATTICES = [(8, 8, 8, 8), (6, 4, 6, 10), (2, 2, 2, 2), (4, 2, 2, 6), (4, 24, 48, 48)]
 
 
 @pytest.fixture(scope="module")
