@@ -33,8 +33,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "Dslash GB/s & %HBM peak at 48^4 SU(2); mixed vs FP64 CG time to 1e-10"
 
-LINK_BYTES = {("fund", "f64"): 64, ("fund", "f32"): 32, ("adj", "f64"): 72, ("adj", "f32"): 36}
-SPINOR_BYTES = {("fund", "f64"): 128, ("fund", "f32"): 64, ("adj", "f64"): 192, ("adj", "f32"): 96}
+LINK_BYTES = {("fund", "f64"): 64, ("fund", "f32"): 32, ("adj", "f64"): 72, ("adj", "f32"): 36,
+              ("fund_su2", "f64"): 32, ("fund_su2", "f32"): 16, ("adj_su2", "f64"): 32, ("adj_su2", "f32"): 16}
+SPINOR_BYTES = {("fund", "f64"): 128, ("fund", "f32"): 64, ("adj", "f64"): 192, ("adj", "f32"): 96,
+                ("fund_su2", "f64"): 128, ("fund_su2", "f32"): 64, ("adj_su2", "f64"): 192, ("adj_su2", "f32"): 96}
 
 
 def hop_alg_bytes(V, rep, prec):
@@ -54,6 +56,49 @@ def dhat_alg_bytes(V, rep, prec):
     """D^ = two hops plus the m*psi read of the second: V (8L + 2.5 S)."""
     L, S = LINK_BYTES[(rep, prec)], SPINOR_BYTES[(rep, prec)]
     return V * (8 * L) + (V // 2) * 5 * S
+
+
+KERNEL_SOURCES = ["paper_2411_18511_amd/csrc/dslash.hip", "paper_2411_18511_amd/csrc/common.h",
+                  "paper_2411_18511_amd/csrc/spin.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_fund_48x48x48x48.traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the hop kernel from the committed counter summary,
+    or None when the kernel sources have changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t
+
+
+def copy_ceiling(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes: the achievable read+write bandwidth on this machine."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_read_plus_written": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def cpu_oracle_sample(U_nat, psi_nat, V, budget_s=10.0):
@@ -118,13 +163,28 @@ def main():
         del rhs_np
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    results = {}
+    LINK_FORMATS = ("fund", "fund_su2")
+
+    def timed(fn, reps):
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps  # ms per application
+
+    def timed_once(fn):
+        a, b = ev(), ev()
+        a.record()
+        out = fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b), out
 
     def step():
         r = {}
-        # 1. gauge preparation
-        U64 = hrd.pack_gauge(U_nat, dims, "fund", "f64")
-        U32 = hrd.convert_gauge(U64, dims, "fund")
+        R = args.reps
         src_all = hrd.pack_spinor(psi_nat, dims, "fund", "f64", "all")
         src_e = hrd.pack_spinor(psi_nat, dims, "fund", "f64", "even")
         src_o = hrd.pack_spinor(psi_nat, dims, "fund", "f64", "odd")
@@ -133,107 +193,89 @@ def main():
         out_e = torch.empty_like(src_e)
         out_e32 = torch.empty_like(src_e32)
         out_all = torch.empty_like(src_all)
-
-        # 2. Dslash phases, HIP events on the library's stream
-        def timed(fn, reps):
-            a, b = ev(), ev()
-            a.record()
-            for _ in range(reps):
-                fn()
-            b.record()
-            b.synchronize()
-            return a.elapsed_time(b) / reps  # ms per application
-
-        R = args.reps
-        hop64 = hrd.DiracOp(U64, dims, "fund", "f64", m0, "hop_eo")
-        hop32 = hrd.DiracOp(U32, dims, "fund", "f32", m0, "hop_eo")
-        full64 = hrd.DiracOp(U64, dims, "fund", "f64", m0, "full")
-        dhat64 = hrd.DiracOp(U64, dims, "fund", "f64", m0, "eo")
-        dhatd64 = hrd.DiracOp(U64, dims, "fund", "f64", m0, "eo", dagger=True)
-        dhat32 = hrd.DiracOp(U32, dims, "fund", "f32", m0, "eo")
-        r["hop_f64_ms"] = timed(lambda: hop64(src_o, out_e), R)
-        r["hop_f32_ms"] = timed(lambda: hop32(src_o32, out_e32), R)
-        r["full_f64_ms"] = timed(lambda: full64(src_all, out_all), R // 2)
-        r["dhat_f64_ms"] = timed(lambda: dhat64(src_e, out_e), R // 2)
-        r["dhat_dag_f64_ms"] = timed(lambda: dhatd64(src_e, out_e), R // 2)
-        r["dhat_f32_ms"] = timed(lambda: dhat32(src_e32, out_e32), R // 2)
-
-        # 3. CG solves (each synchronises internally); events bracket them
-        a, b = ev(), ev()
-        a.record()
-        x64, i64 = hrd.cg_solve(U64, src_e, m0, tol, dims, "fund", mode="f64")
-        b.record()
-        b.synchronize()
-        r["cg_f64_ms"] = a.elapsed_time(b)
-        r["cg_f64"] = i64
-        a, b = ev(), ev()
-        a.record()
-        xm, im = hrd.cg_solve(U64, src_e, m0, tol, dims, "fund", mode="mixed", U32=U32)
-        b.record()
-        b.synchronize()
-        r["cg_mixed_ms"] = a.elapsed_time(b)
-        r["cg_mixed"] = im
-        # x_mixed vs x_f64: both solved to 1e-10
-        n64 = hrd.blas_norm2(x64, dims, "fund", "f64", 1)
-        d = xm.clone()
-        hrd.blas_axpy(-1.0, x64, d, dims, "fund", "f64", 1)
-        r["mixed_vs_f64_rel"] = float(np.sqrt(hrd.blas_norm2(d, dims, "fund", "f64", 1) / n64))
-
-        # 4. fermion force from the mixed solution
-        a, b = ev(), ev()
-        a.record()
-        hrd.action_force(U64, xm, m0, dims, "fund")
-        b.record()
-        b.synchronize()
-        r["action_force_ms"] = a.elapsed_time(b)
-
-        # 5. batched multi-RHS D^ (FP32)
-        if batched_ok:
-            srcs = torch.stack([hrd.convert_spinor(hrd.pack_spinor(t, dims, "fund", "f64", "even"), dims, "fund",
-                                                   1, True) for t in rhs_nat])
-            dsts = torch.empty_like(srcs)
-            probs = hrd.make_problems([{"dims": dims, "rep": "fund", "nrhs": nrhs_batched, "m0": m0, "U32": U32,
-                                        "src": srcs, "dst": dsts}])
-            wb = torch.empty(max(hrd.batched_workspace_bytes(probs, "eo"), 1), dtype=torch.uint8, device=dev)
-            r["batched_dhat_ms"] = timed(lambda: hrd.dirac_apply_batched(probs, "eo", work=wb), 5)
+        for fmt in LINK_FORMATS:
+            # 1. gauge preparation: pack the natural links, FP32 copy
+            U64 = hrd.pack_gauge(U_nat, dims, fmt, "f64")
+            U32 = hrd.convert_gauge(U64, dims, fmt)
+            # 2. Dslash phases, HIP events on the library's stream
+            hop64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "hop_eo")
+            hop32 = hrd.DiracOp(U32, dims, fmt, "f32", m0, "hop_eo")
+            full64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "full")
+            dhat64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "eo")
+            dhatd64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "eo", dagger=True)
+            dhat32 = hrd.DiracOp(U32, dims, fmt, "f32", m0, "eo")
+            r[f"hop_f64_{fmt}"] = timed(lambda: hop64(src_o, out_e), R)
+            r[f"hop_f32_{fmt}"] = timed(lambda: hop32(src_o32, out_e32), R)
+            r[f"full_f64_{fmt}"] = timed(lambda: full64(src_all, out_all), R // 2)
+            r[f"dhat_f64_{fmt}"] = timed(lambda: dhat64(src_e, out_e), R // 2)
+            r[f"dhat_dag_f64_{fmt}"] = timed(lambda: dhatd64(src_e, out_e), R // 2)
+            r[f"dhat_f32_{fmt}"] = timed(lambda: dhat32(src_e32, out_e32), R // 2)
+            # 3. CG solves to 1e-10 (each synchronises internally)
+            r[f"cg_f64_{fmt}_ms"], (x64, i64) = timed_once(
+                lambda: hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="f64"))
+            r[f"cg_mixed_{fmt}_ms"], (xm, im) = timed_once(
+                lambda: hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="mixed", U32=U32))
+            r[f"cg_f64_{fmt}"], r[f"cg_mixed_{fmt}"] = i64, im
+            n64 = hrd.blas_norm2(x64, dims, fmt, "f64", 1)
+            d = xm.clone()
+            hrd.blas_axpy(-1.0, x64, d, dims, fmt, "f64", 1)
+            r[f"mixed_vs_f64_rel_{fmt}"] = float(np.sqrt(hrd.blas_norm2(d, dims, fmt, "f64", 1) / n64))
+            # 4. fermion force from the mixed solution
+            r[f"action_force_{fmt}_ms"], _ = timed_once(lambda: hrd.action_force(U64, xm, m0, dims, fmt))
+            # 5. batched multi-RHS D^ (FP32)
+            if batched_ok:
+                srcs = torch.stack([hrd.convert_spinor(hrd.pack_spinor(t, dims, fmt, "f64", "even"), dims, fmt,
+                                                       1, True) for t in rhs_nat])
+                dsts = torch.empty_like(srcs)
+                probs = hrd.make_problems([{"dims": dims, "rep": fmt, "nrhs": nrhs_batched, "m0": m0, "U32": U32,
+                                            "src": srcs, "dst": dsts}])
+                wb = torch.empty(max(hrd.batched_workspace_bytes(probs, "eo"), 1), dtype=torch.uint8, device=dev)
+                r[f"batched_dhat_{fmt}"] = timed(lambda: hrd.dirac_apply_batched(probs, "eo", work=wb), 5)
+                del srcs, dsts, wb
+            del U64, U32, x64, xm, d
         return r
 
+    ceiling = copy_ceiling(torch, dev)
     for w in range(args.warmup):
         print(f"[bench] warmup {w}", file=sys.stderr, flush=True)
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     per = []
-    for s in range(args.steps):
+    for s_ in range(args.steps):
         per.append(step())
-        print(f"[bench] step {s} done: hop f64 {per[-1]['hop_f64_ms']:.3f} ms, cg f64 {per[-1]['cg_f64_ms']:.1f} ms,"
-              f" cg mixed {per[-1]['cg_mixed_ms']:.1f} ms", file=sys.stderr, flush=True)
+        p = per[-1]
+        print(f"[bench] step {s_} done: hop f64 {p['hop_f64_fund']:.3f} ms, cg f64 {p['cg_f64_fund_ms']:.1f} ms, "
+              f"cg mixed {p['cg_mixed_fund_ms']:.1f} ms, cg mixed su2 {p['cg_mixed_fund_su2_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     def avg(k):
         return float(np.mean([p[k] for p in per]))
 
-    hop_ms = avg("hop_f64_ms")
-    hop_gbs = hop_alg_bytes(V, "fund", "f64") / (hop_ms * 1e-3) / 1e9
-    dslash = {
-        "hop_f64": {"ms": hop_ms, "alg_GBs": hop_gbs, "site_updates_per_s": (V // 2) / (hop_ms * 1e-3)},
-    }
-    for key, fn, prec in [("hop_f32", hop_alg_bytes, "f32"), ("full_f64", full_alg_bytes, "f64"),
-                          ("dhat_f64", dhat_alg_bytes, "f64"), ("dhat_dag_f64", dhat_alg_bytes, "f64"),
-                          ("dhat_f32", dhat_alg_bytes, "f32")]:
-        ms = avg(key + "_ms")
-        sites = V // 2 if key.startswith("hop") else V
-        dslash[key] = {"ms": ms, "alg_GBs": fn(V, "fund", prec) / (ms * 1e-3) / 1e9,
-                       "site_updates_per_s": sites / (ms * 1e-3)}
-    for v in dslash.values():
-        v["pct_hbm_peak"] = 100.0 * v["alg_GBs"] / HBM_PEAK_GBS
-    cg = {
-        "f64": {"ms": avg("cg_f64_ms"), **per[-1]["cg_f64"]},
-        "mixed": {"ms": avg("cg_mixed_ms"), **per[-1]["cg_mixed"]},
-        "mixed_over_f64_time": avg("cg_mixed_ms") / avg("cg_f64_ms"),
-        "mixed_vs_f64_solution_rel_diff": per[-1]["mixed_vs_f64_rel"],
-    }
+    dslash = {}
+    for fmt in LINK_FORMATS:
+        for key, fn, prec in [("hop_f64", hop_alg_bytes, "f64"), ("hop_f32", hop_alg_bytes, "f32"),
+                              ("full_f64", full_alg_bytes, "f64"), ("dhat_f64", dhat_alg_bytes, "f64"),
+                              ("dhat_dag_f64", dhat_alg_bytes, "f64"), ("dhat_f32", dhat_alg_bytes, "f32")]:
+            ms = avg(f"{key}_{fmt}")
+            sites = V // 2 if key.startswith("hop") else V
+            gbs = fn(V, fmt, prec) / (ms * 1e-3) / 1e9
+            dslash[f"{key}_{fmt}"] = {"ms": ms, "alg_GBs": gbs, "pct_hbm_peak": 100.0 * gbs / HBM_PEAK_GBS,
+                                      "site_updates_per_s": sites / (ms * 1e-3),
+                                      "alg_bytes": fn(V, fmt, prec)}
+    cg = {}
+    for fmt in LINK_FORMATS:
+        cg[fmt] = {
+            "f64": {"ms": avg(f"cg_f64_{fmt}_ms"), **per[-1][f"cg_f64_{fmt}"]},
+            "mixed": {"ms": avg(f"cg_mixed_{fmt}_ms"), **per[-1][f"cg_mixed_{fmt}"]},
+            "mixed_over_f64_time": avg(f"cg_mixed_{fmt}_ms") / avg(f"cg_f64_{fmt}_ms"),
+            "mixed_vs_f64_solution_rel_diff": per[-1][f"mixed_vs_f64_rel_{fmt}"],
+            "action_force_ms": avg(f"action_force_{fmt}_ms"),
+        }
+    hop = dslash["hop_f64_fund"]
+    hop_gbs = hop["alg_GBs"]
     out = {
         "metric": METRIC,
         "value": round(hop_gbs, 2),
@@ -248,22 +290,29 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "48^4 SU(2) fundamental Wilson-Dirac, heat-bath-like links (plaquette 0.6), "
-                               "m0=-0.3; Dslash = FP64 hopping block D_eo; CG on D^+D^ to 1e-10",
+                               "m0=-0.3; Dslash = FP64 hopping block D_eo with full 2x2 links; CG on D^+D^ "
+                               "to 1e-10 in FP64 and mixed precision, full and first-row SU(2) link storage",
                    "dims": list(dims), "m0": m0, "tol": tol},
         "roofline": {"bound": "hbm", "achieved": round(hop_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(hop_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "hop_kernel<FUND, double> (no epilogue)",
-                     "alg_bytes_per_launch": hop_alg_bytes(V, "fund", "f64")},
+                     "kernel": "hop_kernel<FUND, double, dagger=false, no epilogue>",
+                     "alg_bytes_per_launch": hop_alg_bytes(V, "fund", "f64"), "avg_launch_ms": hop["ms"]},
         "dslash": dslash,
         "cg": cg,
-        "action_force_ms": avg("action_force_ms"),
+        "copy_ceiling": ceiling,
     }
+    tr = measured_traffic()
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["roofline"]["traffic_source"] = tr["source"]
     if batched_ok:
-        bms = avg("batched_dhat_ms")
-        L, S = LINK_BYTES[("fund", "f32")], SPINOR_BYTES[("fund", "f32")]
-        bbytes = V * 8 * L + (V // 2) * 5 * S * nrhs_batched
-        out["batched"] = {"nrhs": nrhs_batched, "dhat_f32_ms": bms, "alg_GBs": bbytes / (bms * 1e-3) / 1e9,
-                          "ms_per_rhs": bms / nrhs_batched}
+        out["batched"] = {}
+        for fmt in LINK_FORMATS:
+            bms = avg(f"batched_dhat_{fmt}")
+            L, S = LINK_BYTES[(fmt, "f32")], SPINOR_BYTES[(fmt, "f32")]
+            bbytes = V * 8 * L + (V // 2) * 5 * S * nrhs_batched
+            out["batched"][fmt] = {"nrhs": nrhs_batched, "dhat_f32_ms": bms, "alg_GBs": bbytes / (bms * 1e-3) / 1e9,
+                                   "ms_per_rhs": bms / nrhs_batched}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(U_np, psi_np, V)
     print(json.dumps(out), flush=True)

@@ -39,7 +39,7 @@
  * PACKED LAYOUTS ("library layout"; all device memory)
  *   A field of one parity is a sequence of PLANES; a plane is an array of Vh
  *   elements, one per site, in site order.  Spinor components are numbered
- *   k = spin * N + colour (N = 2 FUND, 3 ADJ; 4N components).
+ *   k = spin * N + colour (N = 2 FUND, FUND_SU2; 3 ADJ, ADJ_SU2; 4N components).
  *     spinor, F64 : 4N planes of complex128 (16 B): plane k = component k.
  *     spinor, F32 : 2N planes of 2 x complex64 (16 B): plane k = components
  *                   (2k, 2k+1).
@@ -50,13 +50,17 @@
  *                    e = 3 a + b of R_ab.
  *     link ADJ  F32: 2 planes of 4 x float32 (entries 0-3, 4-7), then 1 plane
  *                    of float32 (entry 8).
+ *     link FUND_SU2, ADJ_SU2 F64: 2 planes of complex128, entries U00, U01 of
+ *                    the fundamental link.
+ *     link FUND_SU2, ADJ_SU2 F32: 1 plane of 2 x complex64: (U00, U01).
  *   A full-lattice spinor is [parity][planes][Vh], even block first.  A
  *   gauge field is [parity][mu][planes][Vh]: block (p, mu) holds the links
  *   U_mu(x) of the sites x of parity p.
  *
  * NATURAL LAYOUTS (device memory; used only by the pack/unpack calls)
  *   spinor : complex128 [V][4][N]          (site lex, spin, colour)
- *   gauge  : complex128 [4][V][2][2] FUND, float64 [4][V][3][3] ADJ
+ *   gauge  : complex128 [4][V][2][2] FUND, FUND_SU2 and ADJ_SU2 (the
+ *            fundamental links), float64 [4][V][3][3] ADJ
  *
  * OWNERSHIP AND ERRORS
  *   Every field pointer is a device pointer owned by the caller; the library
@@ -90,7 +94,15 @@ typedef enum {
     HRD_ESIZE = 7        /* caller-provided workspace too small                */
 } hrd_status;
 
-typedef enum { HRD_FUND = 0, HRD_ADJ = 1 } hrd_rep;
+/* Fermion representation and link storage.  HRD_FUND and HRD_ADJ store the
+   links of that representation.  The _SU2 variants store only the first row
+   (U00, U01) of each fundamental link: an SU(2) matrix is
+   [[a, b], [-conj(b), conj(a)]], so the second row is reconstructed exactly
+   in the kernels, and for HRD_ADJ_SU2 the adjoint matrix R(U) is computed
+   from that row inside the kernels (the quaternion form of R).  This halves
+   (FUND) or cuts by 5/9 (ADJ) the link bytes the operator reads; it assumes
+   the links are exactly of SU(2) form. */
+typedef enum { HRD_FUND = 0, HRD_ADJ = 1, HRD_FUND_SU2 = 2, HRD_ADJ_SU2 = 3 } hrd_rep;
 typedef enum { HRD_F64 = 0, HRD_F32 = 1 } hrd_prec;
 
 /* Which block of D a call applies (Sec. 2.1: the plain operator and the
@@ -142,13 +154,15 @@ size_t hrd_gauge_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec);
 /* ------------------------------------------------------------------------ */
 
 /* Natural -> packed gauge field.  U_nat is complex128 [4][V][2][2] for FUND
-   and float64 [4][V][3][3] for ADJ; U receives hrd_gauge_bytes(lat, rep, prec)
-   bytes (FP32 output is rounded to nearest). */
+   and the _SU2 formats (which keep its first row), float64 [4][V][3][3] for
+   ADJ; U receives hrd_gauge_bytes(lat, rep, prec) bytes (FP32 output is
+   rounded to nearest). */
 hrd_status hrd_pack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
                           const void *U_nat, void *U, void *stream);
 
 /* Packed -> natural gauge field (also used for force fields, which share the
-   gauge layout).  Output dtype as for hrd_pack_gauge, always FP64. */
+   gauge layout).  Output dtype as for hrd_pack_gauge, always FP64; the _SU2
+   formats are returned as full fundamental matrices. */
 hrd_status hrd_unpack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
                             const void *U, void *U_nat, void *stream);
 
@@ -276,8 +290,10 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
      G_mu(x) = -1/2 s_mu(x) sum_spin [ X(x) (x) ((1 - g_mu) Y(x+mu))^*
                                      + ((1 + g_mu) Y(x)) (x) X(x+mu)^* ],
    (a (x) b^*)_ij = a_i conj(b_j).  X and Y are packed full-lattice FP64
-   spinors; F is a packed FP64 gauge-layout field.  For ADJ the links are
-   real and F = scale * Re G.  D is linear in U, so G does not depend on U;
+   spinors; F is a packed FP64 gauge-layout field of the uncompressed
+   representation (FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2),
+   because a derivative is a general matrix.  For ADJ the links are real and
+   F = scale * Re G.  D is linear in U, so G does not depend on U;
    U is accepted so the call mirrors the operator's arguments and may be NULL.
    Asynchronous. */
 hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
@@ -291,7 +307,8 @@ size_t hrd_action_force_workspace_bytes(const hrd_lattice *lat, hrd_rep rep);
    xi = (D^+ D^)^{-1} phi (packed FP64 even half field):
      F = scale * (2/m) G[X, Y],  eta = D^ xi,  Y = (xi, D_oe xi),
      X = (eta, (D_eo)^+ eta),  m = 4 + m0,
-   which is scale * dS/dU.  U is the packed FP64 gauge field.  Asynchronous. */
+   which is scale * dS/dU.  U is the packed FP64 gauge field of rep; F has the
+   uncompressed layout as for hrd_dirac_force.  Asynchronous. */
 hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U,
                             const void *xi, void *F, double m0, double scale,
                             void *work, size_t work_bytes, void *stream);

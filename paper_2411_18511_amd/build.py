@@ -2,7 +2,8 @@
 
 Each ``csrc/*.hip`` file is compiled to an object under ``_build/`` in
 parallel, then linked into ``paper_2411_18511_amd/libhrd.so``.  Packed FP32
-instructions are disabled for all device code.
+instructions are disabled for all device code, and floating-point contraction
+is off (the kernels fuse explicitly where they mean to).
 """
 import concurrent.futures
 import glob
@@ -25,13 +26,16 @@ CFLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: only explicit fmadd() calls fuse, so the same
+    # expression rounds identically in every kernel (batched == single)
+    "-ffp-contract=off",
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, verbose, build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     cmd = ["hipcc", "-c", src, "-o", obj] + CFLAGS
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -43,18 +47,18 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 8, lib_path: str = LIB, build_dir: str = BUILD) -> str:
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir), srcs))
+    tmp = lib_path + ".tmp"
     cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -48,7 +48,7 @@ hrd_status check_lattice(const hrd_lattice *lat)
 
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
 {
-    if (rep != HRD_FUND && rep != HRD_ADJ) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
+    if (rep < HRD_FUND || rep > HRD_ADJ_SU2) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
     if (prec != HRD_F64 && prec != HRD_F32) return fail(HRD_EINVAL, "invalid precision %d", (int)prec);
     return HRD_OK;
 }
@@ -72,7 +72,7 @@ size_t gauge_bytes(const hrd_lattice *lat, int rep, int prec)
     return (size_t)V * 4 * link_bytes(rep, prec);
 }
 
-int ncomp_of(int rep) { return rep == HRD_FUND ? 8 : 12; }
+int ncomp_of(int rep) { return 4 * ncolour(rep); }
 
 // D^ in (even half) -> out (even half), tmp: odd half of the same precision.
 hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, void *tmp,
@@ -98,6 +98,32 @@ hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const voi
     a.parity = 0;
     a.partials = norm_partials;
     return launch_hop(rep, prec, a, dag, true, norm_partials != nullptr, false, st);
+}
+
+hipError_t apply_dhat_dag_update_r(int rep, int prec, const Geom &g, const void *U, const void *q, void *r, void *tmp,
+                                   double m0, const double *sc, double *partials, hipStream_t st)
+{
+    const double m = 4.0 + m0;
+    HopArgs a{};
+    a.g = g;
+    a.U = U;
+    a.src = (const char *)q;
+    a.dst = (char *)tmp;
+    a.a = 0.0;
+    a.b = -0.5;
+    a.parity = 1;
+    hipError_t e = launch_hop(rep, prec, a, true, false, false, false, st);
+    if (e != hipSuccess) return e;
+    a.src = (const char *)tmp;
+    a.self = (const char *)q;
+    a.dst = nullptr;
+    a.a = m;
+    a.b = 0.5 / m;
+    a.parity = 0;
+    a.partials = partials;
+    a.r = r;
+    a.sc = sc;
+    return launch_hop_rupdate(rep, prec, a, st);
 }
 
 hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, const void *in, void *out,
@@ -218,7 +244,7 @@ hrd_status hrd_pack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, co
     HRD_TRY(check_rep_prec(rep, prec));
     if (!U_nat || !U) return fail(HRD_EINVAL, "NULL field pointer");
     const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
-    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_FUND ? 4 * 16 : 9 * 8);
+    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_ADJ ? 9 * 8 : 4 * 16);
     if (overlap(U_nat, nat_bytes, U, gauge_bytes(lat, rep, prec))) return fail(HRD_EALIAS, "output overlaps input");
     const Geom g = make_geom(lat->dims);
     return check_hip(launch_pack_gauge(rep, prec, g, U_nat, U, false, (hipStream_t)stream), "pack_gauge launch");
@@ -230,7 +256,7 @@ hrd_status hrd_unpack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, 
     HRD_TRY(check_rep_prec(rep, prec));
     if (!U_nat || !U) return fail(HRD_EINVAL, "NULL field pointer");
     const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
-    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_FUND ? 4 * 16 : 9 * 8);
+    const size_t nat_bytes = (size_t)V * 4 * (rep == HRD_ADJ ? 9 * 8 : 4 * 16);
     if (overlap(U_nat, nat_bytes, U, gauge_bytes(lat, rep, prec))) return fail(HRD_EALIAS, "output overlaps input");
     const Geom g = make_geom(lat->dims);
     return check_hip(launch_pack_gauge(rep, prec, g, U_nat, const_cast<void *>(U), true, (hipStream_t)stream),
@@ -525,9 +551,9 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
         while (inf.iters < maxiter) {
             CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st), "D^ p");
             CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
-            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st), "D^+ q");
-            CG_HIP(launch_cg_update_r(HRD_F64, n64, w.r64, w.Ap64, w.sc, w.partials, st), "update r");
-            CG_HIP(launch_cg_beta(w.partials, kRedBlocks, w.sc, st), "beta");
+            CG_HIP(apply_dhat_dag_update_r(rep, HRD_F64, g, U64, w.q64, w.r64, w.t64, m0, w.sc, w.partials, st),
+                   "r -= alpha D^+ q");
+            CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
             CG_HIP(launch_cg_update_xp64(n64, x, w.p64, w.r64, w.sc, st), "update x, p");
             inf.iters++;
             {
@@ -563,9 +589,9 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     while (inf.iters < maxiter) {
         CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.p32, w.q32, w.t32, m0, false, w.partials, st), "D^ p");
         CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
-        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.q32, w.Ap32, w.t32, m0, true, nullptr, st), "D^+ q");
-        CG_HIP(launch_cg_update_r(HRD_F32, n32, w.r32, w.Ap32, w.sc, w.partials, st), "update r");
-        CG_HIP(launch_cg_beta(w.partials, kRedBlocks, w.sc, st), "beta");
+        CG_HIP(apply_dhat_dag_update_r(rep, HRD_F32, g, U32, w.q32, w.r32, w.t32, m0, w.sc, w.partials, st),
+               "r -= alpha D^+ q");
+        CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
         inf.iters++;
         {
             hrd_status s = read_scalars(w.sc, sc, st);
@@ -612,7 +638,7 @@ hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
     if (prec != HRD_F64) return fail(HRD_EINVAL, "the force is computed in FP64 only");
     if (!X || !Y || !F) return fail(HRD_EINVAL, "NULL field pointer");
     if (!std::isfinite(scale)) return fail(HRD_EINVAL, "scale is not finite");
-    const size_t sb = spinor_bytes(lat, rep, HRD_F64, 2), fb = gauge_bytes(lat, rep, HRD_F64);
+    const size_t sb = spinor_bytes(lat, rep, HRD_F64, 2), fb = gauge_bytes(lat, base_rep(rep), HRD_F64);
     if (overlap(F, fb, X, sb) || overlap(F, fb, Y, sb)) return fail(HRD_EALIAS, "output overlaps an input");
     const Geom g = make_geom(lat->dims);
     return check_hip(launch_force(rep, g, X, Y, F, scale, (hipStream_t)stream), "force launch");
@@ -634,9 +660,10 @@ hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U, 
     if (!std::isfinite(scale)) return fail(HRD_EINVAL, "scale is not finite");
     const size_t need = 2 * spinor_bytes(lat, rep, HRD_F64, 2);
     if (work_bytes < need) return fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need);
-    const size_t fb = gauge_bytes(lat, rep, HRD_F64), h = spinor_bytes(lat, rep, HRD_F64, 1);
-    if (overlap(F, fb, xi, h) || overlap(F, fb, U, fb) || overlap(work, need, F, fb) || overlap(work, need, xi, h) ||
-        overlap(work, need, U, fb))
+    const size_t fb = gauge_bytes(lat, base_rep(rep), HRD_F64), h = spinor_bytes(lat, rep, HRD_F64, 1);
+    const size_t ub = gauge_bytes(lat, rep, HRD_F64);
+    if (overlap(F, fb, xi, h) || overlap(F, fb, U, ub) || overlap(work, need, F, fb) || overlap(work, need, xi, h) ||
+        overlap(work, need, U, ub))
         return fail(HRD_EALIAS, "buffers overlap");
     const Geom g = make_geom(lat->dims);
     const hipStream_t st = (hipStream_t)stream;

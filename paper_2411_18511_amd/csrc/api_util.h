@@ -27,6 +27,10 @@ int ncomp_of(int rep);
 // ||out||^2 partials (hop_blocks(g) of them).
 hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, void *tmp,
                       double m0, bool dag, double *norm_partials, hipStream_t st);
+// r <- r - alpha (D^+ q), ||r||^2 partials (hop_blocks(g) of them); alpha is
+// read from sc[S_ALPHA] on the device; tmp is an odd half field.
+hipError_t apply_dhat_dag_update_r(int rep, int prec, const Geom &g, const void *U, const void *q, void *r, void *tmp,
+                                   double m0, const double *sc, double *partials, hipStream_t st);
 // out (parity target) = D_{target,1-target} in, or its g5-conjugate.
 hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, const void *in, void *out,
                            int target, bool dag, hipStream_t st);

@@ -163,8 +163,7 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
                 Cx<float> sv[NC];
                 SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)(r0 + k) * d.fbytes, g.Vh, idx, sv);
 #pragma unroll
-                for (int c = 0; c < NC; c++)
-                    out[c] = Cx<float>{ca * sv[c].re + cb * acc[k][c].re, ca * sv[c].im + cb * acc[k][c].im};
+                for (int c = 0; c < NC; c++) out[c] = axpby(ca, sv[c], cb, acc[k][c]);
 #pragma unroll
                 for (int c = 0; c < NC; c++) nrm += (double)out[c].re * out[c].re + (double)out[c].im * out[c].im;
             } else {
@@ -210,10 +209,22 @@ __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs
         const int local = tile - d.tile_base;
         const int sb = local / d.ngroups;
         const int grp = local - sb * d.ngroups;
-        if (d.rep == HRD_FUND)
-            batched_tile<HRD_FUND, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
-        else
-            batched_tile<HRD_ADJ, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+        switch (d.rep) {
+            case HRD_FUND:
+                batched_tile<HRD_FUND, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+                break;
+            case HRD_ADJ:
+                batched_tile<HRD_ADJ, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+                break;
+            case HRD_FUND_SU2:
+                batched_tile<HRD_FUND_SU2, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials,
+                                                         part_stride);
+                break;
+            default:
+                batched_tile<HRD_ADJ_SU2, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials,
+                                                        part_stride);
+                break;
+        }
     }
 }
 
@@ -815,8 +826,9 @@ static std::string tune_key(const hrd_problem *probs, int nprob)
     std::string k = arch + "|batched_hop_f32";
     char buf[128];
     for (int i = 0; i < nprob; i++) {
+        static const char *names[] = {"fund", "adj", "fund_su2", "adj_su2"};
         snprintf(buf, sizeof(buf), "|%dx%dx%dx%d/%s/%d", probs[i].lat.dims[0], probs[i].lat.dims[1], probs[i].lat.dims[2],
-                 probs[i].lat.dims[3], probs[i].rep == HRD_FUND ? "fund" : "adj", probs[i].nrhs);
+                 probs[i].lat.dims[3], names[probs[i].rep], probs[i].nrhs);
         k += buf;
     }
     return k;

@@ -212,29 +212,35 @@ template <typename R>
 __device__ __forceinline__ Cx<R> operator-(Cx<R> a) { return {-a.re, -a.im}; }
 template <typename R>
 __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+// Fused multiply-add with one rounding; with -ffp-contract=off these are the
+// only fused operations, so a given expression rounds identically in every
+// kernel that evaluates it.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // a * b
 template <typename R>
 __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b)
 {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fmadd(a.re, b.re, -a.im * b.im), fmadd(a.re, b.im, a.im * b.re)};
 }
 // conj(a) * b
 template <typename R>
 __device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b)
 {
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fmadd(a.re, b.re, a.im * b.im), fmadd(a.re, b.im, -a.im * b.re)};
 }
 // acc + a * b
 template <typename R>
 __device__ __forceinline__ Cx<R> cfma(Cx<R> a, Cx<R> b, Cx<R> acc)
 {
-    return {acc.re + a.re * b.re - a.im * b.im, acc.im + a.re * b.im + a.im * b.re};
+    return {fmadd(a.re, b.re, fmadd(-a.im, b.im, acc.re)), fmadd(a.re, b.im, fmadd(a.im, b.re, acc.im))};
 }
 // acc + conj(a) * b
 template <typename R>
 __device__ __forceinline__ Cx<R> cfmac(Cx<R> a, Cx<R> b, Cx<R> acc)
 {
-    return {acc.re + a.re * b.re + a.im * b.im, acc.im + a.re * b.im - a.im * b.re};
+    return {fmadd(a.re, b.re, fmadd(a.im, b.im, acc.re)), fmadd(a.re, b.im, fmadd(-a.im, b.re, acc.im))};
 }
 // i * a
 template <typename R>
@@ -307,14 +313,24 @@ struct AdjLink {
     R r[3][3];
 };
 
+__host__ __device__ constexpr bool is_su2_row(int rep) { return rep == HRD_FUND_SU2 || rep == HRD_ADJ_SU2; }
+
+// Number of colours of the fermion in a representation.
+__host__ __device__ constexpr int ncolour(int rep) { return (rep == HRD_FUND || rep == HRD_FUND_SU2) ? 2 : 3; }
+
+// Representation whose (uncompressed) layout a derivative with respect to the
+// links uses: FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2.
+__host__ __device__ constexpr int base_rep(int rep) { return ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ; }
+
 __host__ __device__ constexpr int link_bytes(int rep, int prec)
 {
-    return rep == HRD_FUND ? (prec == HRD_F64 ? 64 : 32) : (prec == HRD_F64 ? 72 : 36);
+    return is_su2_row(rep) ? (prec == HRD_F64 ? 32 : 16)
+                           : rep == HRD_FUND ? (prec == HRD_F64 ? 64 : 32) : (prec == HRD_F64 ? 72 : 36);
 }
 
 __host__ __device__ constexpr int spinor_site_bytes(int rep, int prec)
 {
-    return (rep == HRD_FUND ? 8 : 12) * (prec == HRD_F64 ? 16 : 8);
+    return 4 * ncolour(rep) * (prec == HRD_F64 ? 16 : 8);
 }
 
 template <>
@@ -439,6 +455,94 @@ struct LinkIO<HRD_ADJ, float> {
     }
 };
 
+// First row (a, b) of an SU(2) link U = [[a, b], [-conj(b), conj(a)]].
+template <typename R>
+struct Su2Row {
+    Cx<R> a, b;
+};
+
+template <typename R>
+struct RowIO;
+
+template <>
+struct RowIO<double> {
+    template <bool NT = false>
+    __device__ __forceinline__ static Su2Row<double> load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
+        const vd2 x = ld16d<NT>(b + (size_t)site * 16);
+        const vd2 y = ld16d<NT>(b + ((size_t)Vh + site) * 16);
+        return Su2Row<double>{{x.x, x.y}, {y.x, y.y}};
+    }
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Su2Row<double> &r)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
+        st16d<false>(b + (size_t)site * 16, vd2{r.a.re, r.a.im});
+        st16d<false>(b + ((size_t)Vh + site) * 16, vd2{r.b.re, r.b.im});
+    }
+};
+
+template <>
+struct RowIO<float> {
+    template <bool NT = false>
+    __device__ __forceinline__ static Su2Row<float> load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 16;
+        const vf4 v = ld16f<NT>(b + (size_t)site * 16);
+        return Su2Row<float>{{v.x, v.y}, {v.z, v.w}};
+    }
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Su2Row<float> &r)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 16;
+        st16f<false>(b + (size_t)site * 16, vf4{r.a.re, r.a.im, r.b.re, r.b.im});
+    }
+};
+
+template <typename R>
+struct LinkIO<HRD_FUND_SU2, R> {
+    using Link = FundLink<R>;
+    // second row reconstructed: U10 = -conj(U01), U11 = conj(U00)
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const Su2Row<R> r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
+        Link l;
+        l.u[0][0] = r.a;
+        l.u[0][1] = r.b;
+        l.u[1][0] = Cx<R>{-r.b.re, r.b.im};
+        l.u[1][1] = Cx<R>{r.a.re, -r.a.im};
+        return l;
+    }
+};
+
+template <typename R>
+struct LinkIO<HRD_ADJ_SU2, R> {
+    using Link = AdjLink<R>;
+    // R(U)_ij = (a0^2 - |v|^2) d_ij + 2 v_i v_j + 2 a0 eps_ijk v_k for
+    // U = a0 + i (v1 s1 + v2 s2 + v3 s3), read from the first row
+    // a = a0 + i v3, b = v2 + i v1; this equals tr(s_i U s_j U^+) / 2 for
+    // every U of that form (both sides are quadratic and agree on SU(2)).
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const Su2Row<R> r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
+        const R a0 = r.a.re, v0 = r.b.im, v1 = r.b.re, v2 = r.a.im;
+        const R d = a0 * a0 - (v0 * v0 + v1 * v1 + v2 * v2);
+        const R t0 = 2 * a0 * v0, t1 = 2 * a0 * v1, t2 = 2 * a0 * v2;
+        Link l;
+        l.r[0][0] = d + 2 * v0 * v0;
+        l.r[1][1] = d + 2 * v1 * v1;
+        l.r[2][2] = d + 2 * v2 * v2;
+        l.r[0][1] = 2 * v0 * v1 + t2;
+        l.r[1][0] = 2 * v0 * v1 - t2;
+        l.r[1][2] = 2 * v1 * v2 + t0;
+        l.r[2][1] = 2 * v1 * v2 - t0;
+        l.r[2][0] = 2 * v2 * v0 + t1;
+        l.r[0][2] = 2 * v2 * v0 - t1;
+        return l;
+    }
+};
+
 // Colour multiplication of one spin component: out = U h, or U^+ h.
 template <typename R>
 __device__ __forceinline__ void link_mul(const FundLink<R> &l, const Cx<R> (&h)[2], Cx<R> (&o)[2])
@@ -457,16 +561,16 @@ __device__ __forceinline__ void link_mul(const AdjLink<R> &l, const Cx<R> (&h)[3
 {
 #pragma unroll
     for (int i = 0; i < 3; i++)
-        o[i] = Cx<R>{l.r[i][0] * h[0].re + l.r[i][1] * h[1].re + l.r[i][2] * h[2].re,
-                     l.r[i][0] * h[0].im + l.r[i][1] * h[1].im + l.r[i][2] * h[2].im};
+        o[i] = Cx<R>{fmadd(l.r[i][2], h[2].re, fmadd(l.r[i][1], h[1].re, l.r[i][0] * h[0].re)),
+                     fmadd(l.r[i][2], h[2].im, fmadd(l.r[i][1], h[1].im, l.r[i][0] * h[0].im))};
 }
 template <typename R>
 __device__ __forceinline__ void link_mul_dag(const AdjLink<R> &l, const Cx<R> (&h)[3], Cx<R> (&o)[3])
 {
 #pragma unroll
     for (int i = 0; i < 3; i++)
-        o[i] = Cx<R>{l.r[0][i] * h[0].re + l.r[1][i] * h[1].re + l.r[2][i] * h[2].re,
-                     l.r[0][i] * h[0].im + l.r[1][i] * h[1].im + l.r[2][i] * h[2].im};
+        o[i] = Cx<R>{fmadd(l.r[2][i], h[2].re, fmadd(l.r[1][i], h[1].re, l.r[0][i] * h[0].re)),
+                     fmadd(l.r[2][i], h[2].im, fmadd(l.r[1][i], h[1].im, l.r[0][i] * h[0].im))};
 }
 
 // ---------------------------------------------------------------------------

@@ -99,7 +99,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 // out = a psi_self(x) + b (H psi_src)(x) on the target parity; FULL runs both
 // parities in one launch (blocks alternate parity), NORM writes one partial
 // of ||out||^2 per block.
-template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL>
+template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false>
 __global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
 {
     constexpr int N = NCol<REP>::value;
@@ -142,17 +142,29 @@ __global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
             Cx<R> self_v[NC];
             SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
 #pragma unroll
-            for (int k = 0; k < NC; k++)
-                out[k] = Cx<R>{ca * self_v[k].re + cb * acc[k].re, ca * self_v[k].im + cb * acc[k].im};
+            for (int k = 0; k < NC; k++) out[k] = axpby(ca, self_v[k], cb, acc[k]);
         } else {
 #pragma unroll
             for (int k = 0; k < NC; k++) out[k] = cb * acc[k];
         }
-        SpinorIO<R>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
-        if constexpr (NORM) {
+        if constexpr (RUPD) {
+            // r <- r - alpha out ; out (= A p) itself is never written
+            const R alpha = (R)a.sc[S_ALPHA];
+            Cx<R> rv[NC];
+            SpinorIO<R>::template load<NC>(a.r, g.Vh, idx, rv);
 #pragma unroll
-            for (int k = 0; k < NC; k++)
-                nrm += (double)out[k].re * (double)out[k].re + (double)out[k].im * (double)out[k].im;
+            for (int k = 0; k < NC; k++) {
+                rv[k] = Cx<R>{fmadd(-alpha, out[k].re, rv[k].re), fmadd(-alpha, out[k].im, rv[k].im)};
+                nrm += (double)rv[k].re * (double)rv[k].re + (double)rv[k].im * (double)rv[k].im;
+            }
+            SpinorIO<R>::template store<NC, HRD_NT_STORE>(a.r, g.Vh, idx, rv);
+        } else {
+            SpinorIO<R>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
+            if constexpr (NORM) {
+#pragma unroll
+                for (int k = 0; k < NC; k++)
+                    nrm += (double)out[k].re * (double)out[k].re + (double)out[k].im * (double)out[k].im;
+            }
         }
     }
     if constexpr (NORM) {
@@ -193,19 +205,48 @@ hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool 
     return hipGetLastError();
 }
 
+template <int REP, typename R>
+hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)), dim3(kBlock), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int hop_blocks(const Geom &g) { return (g.Vh + kBlock - 1) / kBlock; }
 
+hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st)
+{
+    const bool d = prec == HRD_F64;
+    switch (rep) {
+        case HRD_FUND: return d ? dispatch_rupd<HRD_FUND, double>(a, st) : dispatch_rupd<HRD_FUND, float>(a, st);
+        case HRD_ADJ: return d ? dispatch_rupd<HRD_ADJ, double>(a, st) : dispatch_rupd<HRD_ADJ, float>(a, st);
+        case HRD_FUND_SU2:
+            return d ? dispatch_rupd<HRD_FUND_SU2, double>(a, st) : dispatch_rupd<HRD_FUND_SU2, float>(a, st);
+        default: return d ? dispatch_rupd<HRD_ADJ_SU2, double>(a, st) : dispatch_rupd<HRD_ADJ_SU2, float>(a, st);
+    }
+}
+
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st)
 {
-    if (rep == HRD_FUND) {
-        if (prec == HRD_F64) return dispatch_hop<HRD_FUND, double>(a, dag, has_a, norm, full, st);
-        return dispatch_hop<HRD_FUND, float>(a, dag, has_a, norm, full, st);
+    const bool d = prec == HRD_F64;
+    switch (rep) {
+        case HRD_FUND:
+            return d ? dispatch_hop<HRD_FUND, double>(a, dag, has_a, norm, full, st)
+                     : dispatch_hop<HRD_FUND, float>(a, dag, has_a, norm, full, st);
+        case HRD_ADJ:
+            return d ? dispatch_hop<HRD_ADJ, double>(a, dag, has_a, norm, full, st)
+                     : dispatch_hop<HRD_ADJ, float>(a, dag, has_a, norm, full, st);
+        case HRD_FUND_SU2:
+            return d ? dispatch_hop<HRD_FUND_SU2, double>(a, dag, has_a, norm, full, st)
+                     : dispatch_hop<HRD_FUND_SU2, float>(a, dag, has_a, norm, full, st);
+        default:
+            return d ? dispatch_hop<HRD_ADJ_SU2, double>(a, dag, has_a, norm, full, st)
+                     : dispatch_hop<HRD_ADJ_SU2, float>(a, dag, has_a, norm, full, st);
     }
-    if (prec == HRD_F64) return dispatch_hop<HRD_ADJ, double>(a, dag, has_a, norm, full, st);
-    return dispatch_hop<HRD_ADJ, float>(a, dag, has_a, norm, full, st);
 }
 
 }  // namespace hrd

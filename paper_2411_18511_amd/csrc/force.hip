@@ -96,7 +96,7 @@ hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, vo
     const dim3 grid(2 * hop_blocks(g)), block(kBlock);
     const char *x = reinterpret_cast<const char *>(X);
     const char *y = reinterpret_cast<const char *>(Y);
-    if (rep == HRD_FUND) hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale);
+    if (base_rep(rep) == HRD_FUND) hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale);
     else hipLaunchKernelGGL(force_kernel<HRD_ADJ>, grid, block, 0, st, g, x, y, F, scale);
     return hipGetLastError();
 }

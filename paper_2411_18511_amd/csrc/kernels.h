@@ -17,11 +17,17 @@ struct HopArgs {
     double *partials;   // NORM: one ||out||^2 partial per block
     int parity;         // target parity (ignored by FULL)
     size_t half_bytes;  // FULL: bytes of one parity block of a spinor
+    void *r;            // RUPD: residual updated in place, r <- r - alpha * out
+    const double *sc;   // RUPD: device scalars (alpha in slot S_ALPHA)
 };
 
 int hop_blocks(const Geom &g);
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st);
+// Second stage of D^+ fused with the CG residual update: out = a self + b H src
+// is not stored; instead r <- r - alpha out and ||r||^2 partials are written
+// (one per block, hop_blocks(g) of them).
+hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st);
 
 // ----- field preparation (pack.hip) ----------------------------------------
 hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,

@@ -60,6 +60,44 @@ __global__ __launch_bounds__(kBlock) void pack_gauge_fund_kernel(Geom g, Cx<doub
     }
 }
 
+// FUND_SU2 / ADJ_SU2: keep the first row of each natural fundamental link;
+// unpacking returns the full matrix with the second row reconstructed.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void pack_gauge_su2_kernel(Geom g, Cx<double> *nat, void *packed, bool unpack)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long V = 2L * g.Vh;
+    if (t >= 4 * V) return;
+    const int mu = (int)(t / V);
+    const long r = t - (long)mu * V;
+    const int p = (int)(r / g.Vh);
+    const int idx = (int)(r - (long)p * g.Vh);
+    const Site s = eo_site(g, idx, p);
+    Cx<double> *e = nat + ((size_t)mu * V + s.lex) * 4;
+    if (!unpack) {
+        const Su2Row<R> row{{(R)e[0].re, (R)e[0].im}, {(R)e[1].re, (R)e[1].im}};
+        RowIO<R>::store(packed, g.Vh, p, mu, idx, row);
+    } else {
+        const Su2Row<R> row = RowIO<R>::load(packed, g.Vh, p, mu, idx);
+        e[0] = Cx<double>{(double)row.a.re, (double)row.a.im};
+        e[1] = Cx<double>{(double)row.b.re, (double)row.b.im};
+        e[2] = Cx<double>{-(double)row.b.re, (double)row.b.im};
+        e[3] = Cx<double>{(double)row.a.re, -(double)row.a.im};
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void convert_gauge_su2_kernel(Geom g, const void *U64, void *U32)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 8L * g.Vh) return;
+    const int pm = (int)(t / g.Vh);
+    const int idx = (int)(t - (long)pm * g.Vh);
+    const int p = pm >> 2, mu = pm & 3;
+    const Su2Row<double> a = RowIO<double>::load(U64, g.Vh, p, mu, idx);
+    const Su2Row<float> b{{(float)a.a.re, (float)a.a.im}, {(float)a.b.re, (float)a.b.im}};
+    RowIO<float>::store(U32, g.Vh, p, mu, idx, b);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void pack_gauge_adj_kernel(Geom g, double *nat, void *packed, bool unpack)
 {
@@ -264,7 +302,7 @@ hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const
     const dim3 grid = grid_for((long)np * g.Vh);
     const Cx<double> *n = reinterpret_cast<const Cx<double> *>(nat);
     char *pk = reinterpret_cast<char *>(packed);
-    if (rep == HRD_FUND) {
+    if (ncolour(rep) == 2) {
         if (prec == HRD_F64) hipLaunchKernelGGL((pack_spinor_kernel<2, double>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
         else hipLaunchKernelGGL((pack_spinor_kernel<2, float>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
     } else {
@@ -278,7 +316,11 @@ hipError_t launch_pack_gauge(int rep, int prec, const Geom &g, const void *nat, 
                              hipStream_t st)
 {
     const dim3 grid = grid_for(8L * g.Vh);
-    if (rep == HRD_FUND) {
+    if (is_su2_row(rep)) {
+        Cx<double> *n = reinterpret_cast<Cx<double> *>(const_cast<void *>(nat));
+        if (prec == HRD_F64) hipLaunchKernelGGL((pack_gauge_su2_kernel<double>), grid, dim3(kBlock), 0, st, g, n, packed, unpack);
+        else hipLaunchKernelGGL((pack_gauge_su2_kernel<float>), grid, dim3(kBlock), 0, st, g, n, packed, unpack);
+    } else if (rep == HRD_FUND) {
         Cx<double> *n = reinterpret_cast<Cx<double> *>(const_cast<void *>(nat));
         if (prec == HRD_F64) hipLaunchKernelGGL((pack_gauge_fund_kernel<double>), grid, dim3(kBlock), 0, st, g, n, packed, unpack);
         else hipLaunchKernelGGL((pack_gauge_fund_kernel<float>), grid, dim3(kBlock), 0, st, g, n, packed, unpack);
@@ -307,7 +349,8 @@ hipError_t launch_represent_backward(const Geom &g, const void *Uf, const void *
 hipError_t launch_convert_gauge(int rep, const Geom &g, const void *U64, void *U32, hipStream_t st)
 {
     const dim3 grid = grid_for(8L * g.Vh);
-    if (rep == HRD_FUND) hipLaunchKernelGGL((convert_gauge_kernel<HRD_FUND>), grid, dim3(kBlock), 0, st, g, U64, U32);
+    if (is_su2_row(rep)) hipLaunchKernelGGL(convert_gauge_su2_kernel, grid, dim3(kBlock), 0, st, g, U64, U32);
+    else if (rep == HRD_FUND) hipLaunchKernelGGL((convert_gauge_kernel<HRD_FUND>), grid, dim3(kBlock), 0, st, g, U64, U32);
     else hipLaunchKernelGGL((convert_gauge_kernel<HRD_ADJ>), grid, dim3(kBlock), 0, st, g, U64, U32);
     return hipGetLastError();
 }

@@ -8,9 +8,17 @@
 
 namespace hrd {
 
+// ca * x + cb * y with one fixed rounding sequence, fma(cb, y, ca * x), so
+// every kernel that forms this combination produces identical bits.
+template <typename R>
+__device__ __forceinline__ Cx<R> axpby(R ca, Cx<R> x, R cb, Cx<R> y)
+{
+    return Cx<R>{fmadd(cb, y.re, ca * x.re), fmadd(cb, y.im, ca * x.im)};
+}
+
 template <int REP>
 struct NCol {
-    static constexpr int value = (REP == HRD_FUND) ? 2 : 3;
+    static constexpr int value = ncolour(REP);
 };
 
 // Upper half spinor of (1 + SIG g_mu) psi in the chiral basis.

@@ -27,7 +27,7 @@ _lib = ctypes.CDLL(LIBPATH)
 
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
-FUND, ADJ = 0, 1
+FUND, ADJ, FUND_SU2, ADJ_SU2 = 0, 1, 2, 3
 F64, F32 = 0, 1
 FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
 SITES_ALL, SITES_EVEN, SITES_ODD = 0, 1, 2
@@ -35,7 +35,8 @@ CG_F64, CG_MIXED = 0, 1
 
 _STATUS_NAMES = {0: "HRD_OK", 1: "HRD_EINVAL", 2: "HRD_ESHAPE", 3: "HRD_EALIAS", 4: "HRD_EHIP",
                  5: "HRD_ENOCONV", 6: "HRD_EBREAKDOWN", 7: "HRD_ESIZE"}
-_REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, FUND: FUND, ADJ: ADJ}
+_REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, "fund_su2": FUND_SU2,
+         "adj_su2": ADJ_SU2, FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2}
 _PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, F64: F64, F32: F32,
           torch.float64: F64, torch.float32: F32}
 _PARITIES = {"full": FULL, "eo": EO, "hop_eo": HOP_EO, "hop_oe": HOP_OE,
@@ -184,7 +185,17 @@ class Geometry:
 
     @property
     def ncolour(self):
-        return 2 if self.rep == FUND else 3
+        return ncolour(self.rep)
+
+
+def ncolour(rep):
+    """Colours of the fermion: 2 for the fundamental formats, 3 for the adjoint ones."""
+    return 2 if _REPS[rep] in (FUND, FUND_SU2) else 3
+
+
+def base_rep(rep):
+    """Uncompressed representation whose gauge layout derivatives use."""
+    return FUND if ncolour(rep) == 2 else ADJ
 
 
 def spinor_bytes(dims, rep, prec, nparity):
@@ -209,7 +220,7 @@ def pack_gauge(U_nat, dims, rep, prec):
 def unpack_gauge(U, dims, rep, prec):
     rep, prec = _REPS[rep], _PRECS[prec]
     V = Geometry(tuple(dims), rep).volume
-    if rep == FUND:
+    if rep != ADJ:
         out = torch.empty((4, V, 2, 2), dtype=torch.complex128, device=U.device)
     else:
         out = torch.empty((4, V, 3, 3), dtype=torch.float64, device=U.device)
@@ -401,7 +412,7 @@ def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=
 def dirac_force(U, X, Y, dims, rep, scale=1.0, prec=F64):
     """F = scale * d/dU Re<X, D[U] Y> (packed FP64 gauge layout)."""
     rep = _REPS[rep]
-    out = _empty(gauge_bytes(dims, rep, F64), X.device)
+    out = _empty(gauge_bytes(dims, base_rep(rep), F64), X.device)
     _check(_lib.hrd_dirac_force(ctypes.byref(lattice(dims)), rep, _PRECS[prec], _ptr(U), _ptr(X), _ptr(Y), _ptr(out),
                                 float(scale), _stream()))
     return out
@@ -410,7 +421,7 @@ def dirac_force(U, X, Y, dims, rep, scale=1.0, prec=F64):
 def action_force(U, xi, m0, dims, rep, scale=1.0):
     """scale * dS/dU for S = phi^+ (D^+ D^)^{-1} phi, given xi = (D^+ D^)^{-1} phi."""
     rep = _REPS[rep]
-    out = _empty(gauge_bytes(dims, rep, F64), xi.device)
+    out = _empty(gauge_bytes(dims, base_rep(rep), F64), xi.device)
     wb = _lib.hrd_action_force_workspace_bytes(ctypes.byref(lattice(dims)), rep)
     work = _empty(wb, xi.device)
     _check(_lib.hrd_action_force(ctypes.byref(lattice(dims)), rep, _ptr(U), _ptr(xi), _ptr(out), float(m0),

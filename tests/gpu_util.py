@@ -53,16 +53,20 @@ class Field:
         h = hrd()
         self.dims = tuple(dims)
         self.rep = rep
-        self.n = 2 if rep == "fund" else 3
+        self.n = 2 if rep in ("fund", "fund_su2") else 3
         self.Uf = inputs.gauge_field(dims, seed, kind=kind)
         self.Uf_dev = to_dev_gauge(self.Uf)
         Uf64 = h.pack_gauge(self.Uf_dev, dims, "fund", "f64")
-        if rep == "fund":
+        if self.n == 2:
             self.U_orc = self.Uf
-            self.U64 = Uf64
         else:
             self.U_orc = O.represent_adjoint(self.Uf).astype(np.complex128)
+        if rep == "fund":
+            self.U64 = Uf64
+        elif rep == "adj":
             self.U64 = h.represent(Uf64, dims, "f64")
+        else:  # links stored as the first row of the fundamental matrix
+            self.U64 = h.pack_gauge(self.Uf_dev, dims, rep, "f64")
         self.Uf64 = Uf64
         self.U32 = h.convert_gauge(self.U64, dims, rep)
 
