@@ -230,12 +230,24 @@ def main():
                 probs = hrd.make_problems([{"dims": dims, "rep": fmt, "nrhs": nrhs_batched, "m0": m0, "U32": U32,
                                             "src": srcs, "dst": dsts}])
                 wb = torch.empty(max(hrd.batched_workspace_bytes(probs, "eo"), 1), dtype=torch.uint8, device=dev)
-                r[f"batched_dhat_{fmt}"] = timed(lambda: hrd.dirac_apply_batched(probs, "eo", work=wb), 5)
+                r[f"batched_dhat_{fmt}"] = timed(lambda: hrd.dirac_apply_batched(probs, "eo", tune=tunes[fmt],
+                                                                                 work=wb), 5)
                 del srcs, dsts, wb
             del U64, U32, x64, xm, d
         return r
 
     ceiling = copy_ceiling(torch, dev)
+    tunes = {}
+    if batched_ok:
+        # launch shape of the batched stages, chosen by the library's autotuner (untimed setup)
+        for fmt in LINK_FORMATS:
+            U32t = hrd.convert_gauge(hrd.pack_gauge(U_nat, dims, fmt, "f64"), dims, fmt)
+            srcs = torch.zeros((nrhs_batched, hrd.spinor_bytes(dims, fmt, "f32", 1)), dtype=torch.uint8, device=dev)
+            probs = hrd.make_problems([{"dims": dims, "rep": fmt, "nrhs": nrhs_batched, "m0": m0, "U32": U32t,
+                                        "src": srcs, "dst": torch.zeros_like(srcs)}])
+            tunes[fmt] = hrd.autotune_batched(probs)
+            print(f"[bench] batched tune {fmt}: {tunes[fmt]}", file=sys.stderr, flush=True)
+            del U32t, srcs, probs
     for w in range(args.warmup):
         print(f"[bench] warmup {w}", file=sys.stderr, flush=True)
         step()
@@ -312,7 +324,8 @@ def main():
             L, S = LINK_BYTES[(fmt, "f32")], SPINOR_BYTES[(fmt, "f32")]
             bbytes = V * 8 * L + (V // 2) * 5 * S * nrhs_batched
             out["batched"][fmt] = {"nrhs": nrhs_batched, "dhat_f32_ms": bms, "alg_GBs": bbytes / (bms * 1e-3) / 1e9,
-                                   "ms_per_rhs": bms / nrhs_batched}
+                                   "ms_per_rhs": bms / nrhs_batched, "tune": tunes[fmt],
+                                   "single_dhat_f32_ms": avg(f"dhat_f32_{fmt}")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(U_np, psi_np, V)
     print(json.dumps(out), flush=True)

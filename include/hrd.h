@@ -331,14 +331,17 @@ typedef struct {
     void *dst;         /* nrhs consecutive packed half fields                    */
 } hrd_problem;
 
-/* Launch shape of the batched kernels: sites per tile (a multiple of 64),
-   right-hand sides processed per tile, threads per workgroup, and
-   workgroups per CU of the persistent grid.  Zero fields select defaults. */
+/* Launch shape of the batched kernels: sites per tile (64, 128 or 256; one
+   thread per site, so also the threads per workgroup), right-hand sides
+   processed per tile (1, 2, 3, 4 or 6), workgroups per CU of the persistent
+   grid, and the x1-slab width of the traversal (rounded down to a divisor of
+   each problem's L1).  Zero fields select defaults. */
 typedef struct {
     int sites_per_tile;
     int rhs_per_tile;
     int block_threads;
     int blocks_per_cu;
+    int slab_width;
 } hrd_tune;
 
 /* Workspace bytes for hrd_dirac_apply_batched with parity (HRD_EO needs one
@@ -370,7 +373,8 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
 /* Times candidate launch shapes of the batched hopping kernel on these
    problems (work as for hrd_dirac_apply_batched with HRD_EO; src/dst are
    overwritten) and writes the fastest to *best (median of 5 timed launches
-   per candidate; ties go to the smaller tile).  If cache_path is not NULL the
+   per candidate over tile sizes, group sizes, grid sizes and slab widths;
+   ties go to the earlier, smaller candidate).  If cache_path is not NULL the
    result is looked up in / appended to that JSON-lines file, keyed by the
    GPU architecture and the problem list.  Synchronises. */
 hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, void *work,

@@ -58,124 +58,112 @@ struct RhsDesc {
 
 enum BatchMode { M_NORMAL = 0, M_RELIABLE = 1, M_DONE = 2 };
 
-template <int MU, bool DAG, int REP, int G>
-__device__ __forceinline__ void hop_dir_multi(const Geom &g, const Site &s, int idx, int p, const void *U,
-                                              const char *src, size_t fbytes, const bool (&act)[G],
-                                              Cx<float> (&acc)[G][4 * NCol<REP>::value])
+// One direction of the stencil for one right-hand side, with the link
+// already in registers: project the neighbour spinor, apply the boundary sign,
+// multiply by U (forward) or U^+ (backward), reconstruct and accumulate.
+template <int MU, int SIG, bool BWD, int REP>
+__device__ __forceinline__ void dir_term(const typename LinkIO<REP, float>::Link &l, const char *src, int Vh, int j,
+                                         bool neg, Cx<float> (&acc)[4 * NCol<REP>::value])
 {
     constexpr int N = NCol<REP>::value;
     constexpr int NC = 4 * N;
-    constexpr int SF = DAG ? +1 : -1;
-    constexpr int SB = -SF;
-    using IO = SpinorIO<float>;
-    using LIO = LinkIO<REP, float>;
-    {
-        const int j = nbr_fwd(g, s, MU);
-        const auto l = LIO::template load<true>(U, g.Vh, p, MU, idx);
-        const bool neg = (MU == 0 && s.x[0] == g.L[0] - 1);
+    Cx<float> psi[NC];
+    SpinorIO<float>::template load<NC>(src, Vh, j, psi);
+    Cx<float> h0[N], h1[N], u0[N], u1[N];
+    project<MU, SIG, N, float>(psi, h0, h1);
+    if (neg) {
 #pragma unroll
-        for (int k = 0; k < G; k++) {
-            if (!act[k]) continue;
-            Cx<float> psi[NC];
-            IO::template load<NC>(src + (size_t)k * fbytes, g.Vh, j, psi);
-            Cx<float> h0[N], h1[N], u0[N], u1[N];
-            project<MU, SF, N, float>(psi, h0, h1);
-            if (neg) {
-#pragma unroll
-                for (int c = 0; c < N; c++) {
-                    h0[c] = -h0[c];
-                    h1[c] = -h1[c];
-                }
-            }
-            link_mul(l, h0, u0);
-            link_mul(l, h1, u1);
-            reconstruct<MU, SF, N, float>(acc[k], u0, u1);
+        for (int c = 0; c < N; c++) {
+            h0[c] = -h0[c];
+            h1[c] = -h1[c];
         }
     }
-    {
-        const int j = nbr_bwd(g, s, MU);
-        const auto l = LIO::template load<true>(U, g.Vh, 1 - p, MU, j);
-        const bool neg = (MU == 0 && s.x[0] == 0);
-#pragma unroll
-        for (int k = 0; k < G; k++) {
-            if (!act[k]) continue;
-            Cx<float> psi[NC];
-            IO::template load<NC>(src + (size_t)k * fbytes, g.Vh, j, psi);
-            Cx<float> h0[N], h1[N], u0[N], u1[N];
-            project<MU, SB, N, float>(psi, h0, h1);
-            if (neg) {
-#pragma unroll
-                for (int c = 0; c < N; c++) {
-                    h0[c] = -h0[c];
-                    h1[c] = -h1[c];
-                }
-            }
-            link_mul_dag(l, h0, u0);
-            link_mul_dag(l, h1, u1);
-            reconstruct<MU, SB, N, float>(acc[k], u0, u1);
-        }
+    if constexpr (BWD) {
+        link_mul_dag(l, h0, u0);
+        link_mul_dag(l, h1, u1);
+    } else {
+        link_mul(l, h0, u0);
+        link_mul(l, h1, u1);
     }
+    reconstruct<MU, SIG, N, float>(acc, u0, u1);
 }
 
 // One tile: sites [sb * blockDim, +blockDim) of the target parity, right-hand
-// sides [grp * G, +G) of the problem.  EPI2: out = m self + acc / (2m), plus
-// per-right-hand-side ||out||^2 partials when `partials` is not NULL; else
-// out = -acc / 2.
-template <int REP, int G, bool DAG, bool EPI2>
-__device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp, int parity, int src_id, int self_id,
-                                             int dst_id, const int *mode, double *partials, int part_stride)
+// sides [grp * G, +G) of the problem.  Each thread loads its site's 8 links
+// once into registers and then applies them to the right-hand sides one
+// after another (each with all 8 neighbour loads in flight), so the
+// register footprint does not grow with G.  EPI2: out = m self + acc / (2m),
+// plus per-right-hand-side ||out||^2 partials when `partials` is not NULL;
+// else out = -acc / 2.
+template <int REP, bool DAG, bool EPI2>
+__device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp, int G, int parity, int src_id,
+                                             int self_id, int dst_id, const int *mode, double *partials,
+                                             int part_stride)
 {
     constexpr int NC = 4 * NCol<REP>::value;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    using LIO = LinkIO<REP, float>;
     const Geom &g = d.g;
     const int r0 = grp * G;
-    bool act[G];
+    const int gcount = min(G, d.nrhs - r0);  // >= 1: groups start below nrhs
     bool any = false;
-#pragma unroll
-    for (int k = 0; k < G; k++) {
-        act[k] = (r0 + k < d.nrhs) && (!mode || mode[d.rhs_base + r0 + k] != M_DONE);
-        any = any || act[k];
-    }
+    for (int k = 0; k < gcount; k++) any = any || !mode || mode[d.rhs_base + r0 + k] != M_DONE;
     if (!any) return;  // uniform across the block
     const int w = sb * (int)blockDim.x + (int)threadIdx.x;
     const bool in = w < g.Vh;
-    Cx<float> acc[G][NC];
-#pragma unroll
-    for (int k = 0; k < G; k++)
-#pragma unroll
-        for (int c = 0; c < NC; c++) acc[k][c] = Cx<float>{0.f, 0.f};
     int idx = 0;
-    const char *src = d.buf[src_id] + (size_t)r0 * d.fbytes;
+    int jf[4] = {0, 0, 0, 0}, jb[4] = {0, 0, 0, 0};
+    bool nf = false, nb = false;
+    typename LIO::Link lf[4], lb[4];
     if (in) {
         const Site s = slab_site(g, w, parity, &idx);
-        hop_dir_multi<0, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
-        hop_dir_multi<1, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
-        hop_dir_multi<2, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
-        hop_dir_multi<3, DAG, REP, G>(g, s, idx, parity, d.U32, src, d.fbytes, act, acc);
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            jf[mu] = nbr_fwd(g, s, mu);
+            jb[mu] = nbr_bwd(g, s, mu);
+            lf[mu] = LIO::template load<true>(d.U32, g.Vh, parity, mu, idx);
+            lb[mu] = LIO::template load<true>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
+        }
+        nf = s.x[0] == g.L[0] - 1;
+        nb = s.x[0] == 0;
     }
     const float ca = (float)d.m, cb = EPI2 ? (float)(0.5 / d.m) : -0.5f;
-#pragma unroll
-    for (int k = 0; k < G; k++) {
-        if (!act[k]) continue;
+#pragma unroll 1
+    for (int k = 0; k < gcount; k++) {
+        const int rhs = r0 + k;
+        if (mode && mode[d.rhs_base + rhs] == M_DONE) continue;  // uniform
         double nrm = 0;
         if (in) {
+            const char *src = d.buf[src_id] + (size_t)rhs * d.fbytes;
+            Cx<float> acc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) acc[c] = Cx<float>{0.f, 0.f};
+            dir_term<0, SF, false, REP>(lf[0], src, g.Vh, jf[0], nf, acc);
+            dir_term<0, SB, true, REP>(lb[0], src, g.Vh, jb[0], nb, acc);
+            dir_term<1, SF, false, REP>(lf[1], src, g.Vh, jf[1], false, acc);
+            dir_term<1, SB, true, REP>(lb[1], src, g.Vh, jb[1], false, acc);
+            dir_term<2, SF, false, REP>(lf[2], src, g.Vh, jf[2], false, acc);
+            dir_term<2, SB, true, REP>(lb[2], src, g.Vh, jb[2], false, acc);
+            dir_term<3, SF, false, REP>(lf[3], src, g.Vh, jf[3], false, acc);
+            dir_term<3, SB, true, REP>(lb[3], src, g.Vh, jb[3], false, acc);
             Cx<float> out[NC];
             if constexpr (EPI2) {
                 Cx<float> sv[NC];
-                SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)(r0 + k) * d.fbytes, g.Vh, idx, sv);
+                SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)rhs * d.fbytes, g.Vh, idx, sv);
 #pragma unroll
-                for (int c = 0; c < NC; c++) out[c] = axpby(ca, sv[c], cb, acc[k][c]);
+                for (int c = 0; c < NC; c++) out[c] = axpby(ca, sv[c], cb, acc[c]);
 #pragma unroll
                 for (int c = 0; c < NC; c++) nrm += (double)out[c].re * out[c].re + (double)out[c].im * out[c].im;
             } else {
 #pragma unroll
-                for (int c = 0; c < NC; c++) out[c] = cb * acc[k][c];
+                for (int c = 0; c < NC; c++) out[c] = cb * acc[c];
             }
-            SpinorIO<float>::template store<NC, true>(d.buf[dst_id] + (size_t)(r0 + k) * d.fbytes, g.Vh, idx, out);
+            SpinorIO<float>::template store<NC, true>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, out);
         }
         if (EPI2 && partials != nullptr) {
             // block-wide sum of ||out||^2, only when the caller wants it (a
             // uniform kernel argument); every thread of the block reaches it
-            // since act[k] is uniform
             __shared__ double part[16];
             for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
             if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nrm;
@@ -183,17 +171,17 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
             if (threadIdx.x == 0) {
                 double t = 0;
                 for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) t += part[wv];
-                partials[(size_t)(d.rhs_base + r0 + k) * part_stride + sb] = t;
+                partials[(size_t)(d.rhs_base + rhs) * part_stride + sb] = t;
             }
             __syncthreads();
         }
     }
 }
 
-template <int G, bool DAG, bool EPI2>
-__global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs, int nprob, int ntiles, int parity,
-                                                          int src_id, int self_id, int dst_id, const int *mode,
-                                                          double *partials, int part_stride)
+template <bool DAG, bool EPI2>
+__global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs, int nprob, int ntiles, int G,
+                                                          int parity, int src_id, int self_id, int dst_id,
+                                                          const int *mode, double *partials, int part_stride)
 {
     // each XCD walks its own contiguous range of tiles (gridDim.x is a multiple of 8)
     const int xcd = blockIdx.x % kNumXcd;
@@ -211,18 +199,20 @@ __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs
         const int grp = local - sb * d.ngroups;
         switch (d.rep) {
             case HRD_FUND:
-                batched_tile<HRD_FUND, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+                batched_tile<HRD_FUND, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
+                                                  part_stride);
                 break;
             case HRD_ADJ:
-                batched_tile<HRD_ADJ, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials, part_stride);
+                batched_tile<HRD_ADJ, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
+                                                 part_stride);
                 break;
             case HRD_FUND_SU2:
-                batched_tile<HRD_FUND_SU2, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials,
-                                                         part_stride);
+                batched_tile<HRD_FUND_SU2, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
+                                                      part_stride);
                 break;
             default:
-                batched_tile<HRD_ADJ_SU2, G, DAG, EPI2>(d, sb, grp, parity, src_id, self_id, dst_id, mode, partials,
-                                                        part_stride);
+                batched_tile<HRD_ADJ_SU2, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
+                                                     part_stride);
                 break;
         }
     }
@@ -380,12 +370,13 @@ hrd_status check_problems(const hrd_problem *probs, int nprob, bool need_u64)
 
 hrd_tune resolve_tune(const hrd_tune *t)
 {
-    hrd_tune r{128, 4, 128, 4};
+    hrd_tune r{128, 4, 128, 4, 0};
     if (t) {
         if (t->sites_per_tile > 0) r.sites_per_tile = t->sites_per_tile;
         if (t->rhs_per_tile > 0) r.rhs_per_tile = t->rhs_per_tile;
         if (t->block_threads > 0) r.block_threads = t->block_threads;
         if (t->blocks_per_cu > 0) r.blocks_per_cu = t->blocks_per_cu;
+        if (t->slab_width > 0) r.slab_width = t->slab_width;
     }
     r.block_threads = r.sites_per_tile;  // one thread per site of a tile
     return r;
@@ -395,10 +386,28 @@ hrd_status check_tune(const hrd_tune &t)
 {
     if (t.sites_per_tile != 64 && t.sites_per_tile != 128 && t.sites_per_tile != 256)
         return fail(HRD_EINVAL, "sites_per_tile must be 64, 128 or 256");
-    if (t.rhs_per_tile != 1 && t.rhs_per_tile != 2 && t.rhs_per_tile != 3 && t.rhs_per_tile != 4 && t.rhs_per_tile != 6)
-        return fail(HRD_EINVAL, "rhs_per_tile must be 1, 2, 3, 4 or 6");
+    if (t.rhs_per_tile < 1 || t.rhs_per_tile > kMaxRhs) return fail(HRD_EINVAL, "rhs_per_tile must be in 1..%d", kMaxRhs);
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return fail(HRD_EINVAL, "blocks_per_cu must be in 1..16");
+    if (t.slab_width < 0) return fail(HRD_EINVAL, "slab_width must be >= 0");
     return HRD_OK;
+}
+
+// x1-slab width of a problem's traversal: the requested width rounded down to
+// a divisor of L1, or, when 0, the widest slab whose t-slice holds at most
+// 6912 sites counting each of the G right-hand sides swept together (the same
+// budget as the single-right-hand-side operator).
+int batched_slab(const int dims[4], int G, int requested)
+{
+    int best = 1;
+    if (requested > 0) {
+        for (int b = 1; b <= dims[1] && b <= requested; b++)
+            if (dims[1] % b == 0) best = b;
+        return best;
+    }
+    const long R = (long)dims[2] * dims[3] / 2;
+    for (int b = 1; b <= dims[1]; b++)
+        if (dims[1] % b == 0 && (long)b * R * G <= 6912) best = b;
+    return best;
 }
 
 // Fill the descriptor table; returns total tiles.
@@ -409,7 +418,7 @@ int build_descs(const hrd_problem *probs, int nprob, const hrd_tune &t, std::vec
     *max_nsb = 0;
     for (int i = 0; i < nprob; i++) {
         BatchDesc &b = d[i];
-        b.g = make_geom(probs[i].lat.dims);
+        b.g = make_geom(probs[i].lat.dims, batched_slab(probs[i].lat.dims, t.rhs_per_tile, t.slab_width));
         b.rep = probs[i].rep;
         b.nrhs = probs[i].nrhs;
         b.rhs_base = rhs;
@@ -427,28 +436,14 @@ int build_descs(const hrd_problem *probs, int nprob, const hrd_tune &t, std::vec
     return tiles;
 }
 
-template <int G, bool DAG, bool EPI2>
-void launch_g(int grid, int block, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity, int s,
-              int self, int dst, const int *mode, double *parts, int ps)
-{
-    hipLaunchKernelGGL((batched_hop_kernel<G, DAG, EPI2>), dim3(grid), dim3(block), 0, st, dd, nprob, ntiles, parity,
-                       s, self, dst, mode, parts, ps);
-}
-
 template <bool DAG, bool EPI2>
 hipError_t launch_stage_t(const hrd_tune &t, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity,
                           int s, int self, int dst, const int *mode, double *parts, int ps)
 {
     int grid = kNumCu * t.blocks_per_cu;
     grid = (grid / kNumXcd) * kNumXcd;
-    const int blk = t.sites_per_tile;
-    switch (t.rhs_per_tile) {
-        case 1: launch_g<1, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
-        case 2: launch_g<2, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
-        case 3: launch_g<3, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
-        case 4: launch_g<4, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
-        default: launch_g<6, DAG, EPI2>(grid, blk, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps); break;
-    }
+    hipLaunchKernelGGL((batched_hop_kernel<DAG, EPI2>), dim3(grid), dim3(t.sites_per_tile), 0, st, dd, nprob, ntiles,
+                       t.rhs_per_tile, parity, s, self, dst, mode, parts, ps);
     return hipGetLastError();
 }
 
@@ -845,8 +840,8 @@ static bool cache_lookup(const char *path, const std::string &key, hrd_tune *out
         if (strstr(line, pat.c_str())) {
             hrd_tune t{};
             const char *p = strstr(line, "\"tune\": [");
-            if (p && sscanf(p, "\"tune\": [%d, %d, %d, %d]", &t.sites_per_tile, &t.rhs_per_tile, &t.block_threads,
-                            &t.blocks_per_cu) == 4) {
+            if (p && sscanf(p, "\"tune\": [%d, %d, %d, %d, %d]", &t.sites_per_tile, &t.rhs_per_tile,
+                            &t.block_threads, &t.blocks_per_cu, &t.slab_width) == 5) {
                 *out = t;
                 found = true;
             }
@@ -868,14 +863,16 @@ extern "C" hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, 
     HRD_TRY(check_hip(hipEventCreate(&e0), "event"));
     HRD_TRY(check_hip(hipEventCreate(&e1), "event"));
     const int sites[] = {64, 128, 256};
-    const int groups[] = {1, 2, 3, 4, 6};
+    const int groups[] = {1, 2, 4, 6, 12};
     const int bpc[] = {2, 4, 8};
+    const int slabs[] = {0, 1, 2, 4, 8, 1 << 20};  // 0: automatic; 1 << 20: whole L1 (lexicographic)
     float best_ms = 1e30f;
     hrd_tune bt{};
     for (int s : sites)
         for (int gsz : groups)
-            for (int b : bpc) {
-                const hrd_tune cand{s, gsz, s, b};
+            for (int b : bpc)
+              for (int sl : slabs) {
+                const hrd_tune cand{s, gsz, s, b, sl};
                 hrd_status rc = hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream);
                 if (rc != HRD_OK) {
                     (void)hipEventDestroy(e0);
@@ -904,8 +901,8 @@ extern "C" hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, 
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "{\"key\": \"%s\", \"tune\": [%d, %d, %d, %d], \"median_ms\": %.6f}\n", key.c_str(),
-                    bt.sites_per_tile, bt.rhs_per_tile, bt.block_threads, bt.blocks_per_cu, best_ms);
+            fprintf(f, "{\"key\": \"%s\", \"tune\": [%d, %d, %d, %d, %d], \"median_ms\": %.6f}\n", key.c_str(),
+                    bt.sites_per_tile, bt.rhs_per_tile, bt.block_threads, bt.blocks_per_cu, bt.slab_width, best_ms);
             fclose(f);
         }
     }

@@ -73,7 +73,7 @@ class Problem(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("sites_per_tile", ctypes.c_int), ("rhs_per_tile", ctypes.c_int),
-                ("block_threads", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
+                ("block_threads", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("slab_width", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

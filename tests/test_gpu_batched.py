@@ -49,7 +49,11 @@ SMALL = [((4, 4, 4, 4), "fund", 3, -0.2), ((6, 4, 6, 10), "adj", 5, -0.5), ((8, 
 @pytest.mark.parametrize("tune", [None, {"sites_per_tile": 64, "rhs_per_tile": 3, "block_threads": 64,
                                          "blocks_per_cu": 2},
                                   {"sites_per_tile": 256, "rhs_per_tile": 6, "block_threads": 256,
-                                   "blocks_per_cu": 8}])
+                                   "blocks_per_cu": 8},
+                                  {"sites_per_tile": 128, "rhs_per_tile": 12, "block_threads": 128,
+                                   "blocks_per_cu": 4, "slab_width": 2},
+                                  {"sites_per_tile": 64, "rhs_per_tile": 2, "block_threads": 64,
+                                   "blocks_per_cu": 4, "slab_width": 1}])
 def test_batched_equals_single(oracle, parity, dagger, tune):
     h = hrd()
     ps = _problem_set(SMALL, oracle)
@@ -162,7 +166,7 @@ def test_autotune_and_cache(oracle):
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.jsonl")
         best = h.autotune_batched(probs, cache_path=path)
-        assert best["sites_per_tile"] in (64, 128, 256) and best["rhs_per_tile"] in (1, 2, 3, 4, 6)
+        assert best["sites_per_tile"] in (64, 128, 256) and best["rhs_per_tile"] in (1, 2, 4, 6, 12)
         assert os.path.exists(path) and "gfx" in open(path).read()
         again = h.autotune_batched(probs, cache_path=path)
         assert again == best
