@@ -122,6 +122,57 @@ def cpu_oracle_sample(U_nat, psi_nat, V, budget_s=10.0):
                       f"same algorithmic byte count per application as the GPU figure"}
 
 
+def mixed_volume_cg(torch, hrd, inputs, dev, nrhs=12, tol=1e-10):
+    """12 right-hand sides on each of 16^4, 24^3x48 and 32^4, fundamental and
+    adjoint (Haar links): one batched mixed-precision CG against the same 72
+    systems solved one after another with the single-system mixed CG.  Timed
+    once, outside the per-step figures."""
+    specs = [((16, 16, 16, 16), "fund", -0.3), ((48, 24, 24, 24), "fund", -0.3), ((32, 32, 32, 32), "fund", -0.3),
+             ((16, 16, 16, 16), "adj", -0.5), ((48, 24, 24, 24), "adj", -0.5), ((32, 32, 32, 32), "adj", -0.5)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4)
+    probs_spec, keep = [], []
+    for i, (dims, rep, m0) in enumerate(specs):
+        V = int(np.prod(dims))
+        n = 2 if rep == "fund" else 3
+        Uf = torch.from_numpy(inputs.gauge_field(dims, 40 + i).reshape(4, V, 2, 2)).to(dev)
+        Uf64 = hrd.pack_gauge(Uf, dims, "fund", "f64")
+        U64 = Uf64 if rep == "fund" else hrd.represent(Uf64, dims, "f64")
+        U32 = hrd.convert_gauge(U64, dims, rep)
+        srcs = []
+        for k in range(nrhs):
+            z = torch.complex(torch.randn((V, 4, n), dtype=torch.float64, device=dev, generator=gen),
+                              torch.randn((V, 4, n), dtype=torch.float64, device=dev, generator=gen)) * (0.5 ** 0.5)
+            srcs.append(hrd.pack_spinor(z, dims, rep, "f64", "even"))
+        src = torch.stack(srcs)
+        dst = torch.zeros_like(src)
+        keep.append((dims, rep, m0, U64, U32, src, dst))
+        probs_spec.append({"dims": dims, "rep": rep, "nrhs": nrhs, "m0": m0, "U32": U32, "U64": U64, "src": src,
+                           "dst": dst})
+    probs = hrd.make_problems(probs_spec)
+    work = torch.empty(hrd._lib.hrd_cg_batched_workspace_bytes(probs, len(probs)), dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    infos, status = hrd.cg_solve_batched(probs, tol, work=work)
+    e1.record()
+    e1.synchronize()
+    batched_ms = e0.elapsed_time(e1)
+    e0.record()
+    seq_iters = []
+    for dims, rep, m0, U64, U32, src, dst in keep:
+        for k in range(nrhs):
+            x, inf = hrd.cg_solve(U64, src[k], m0, tol, dims, rep, mode="mixed", U32=U32)
+            seq_iters.append(inf["iters"])
+    e1.record()
+    e1.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    return {"problems": [f"{'x'.join(map(str, d))}/{r}" for d, r, _ in specs], "nrhs_each": nrhs,
+            "status": status, "batched_ms": batched_ms, "sequential_single_ms": seq_ms,
+            "speedup": seq_ms / batched_ms, "max_true_rel_residual": max(i["true_rel_residual"] for i in infos),
+            "iters_batched_max": max(i["iters"] for i in infos), "iters_single_max": max(seq_iters)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +182,7 @@ def main():
     ap.add_argument("--dims", type=str, default="48,48,48,48")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-config4", action="store_true", help="skip the mixed-volume batched CG comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the lattice is not sharded "
@@ -326,6 +378,8 @@ def main():
             out["batched"][fmt] = {"nrhs": nrhs_batched, "dhat_f32_ms": bms, "alg_GBs": bbytes / (bms * 1e-3) / 1e9,
                                    "ms_per_rhs": bms / nrhs_batched, "tune": tunes[fmt],
                                    "single_dhat_f32_ms": avg(f"dhat_f32_{fmt}")}
+    if batched_ok and not args.no_config4:
+        out["batched_cg_mixed_volumes"] = mixed_volume_cg(torch, hrd, inputs, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(U_np, psi_np, V)
     print(json.dumps(out), flush=True)

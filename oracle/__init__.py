@@ -57,6 +57,7 @@ def _load():
         lib.oracle_force.argtypes = [P, ctypes.c_int, P, P, P]
         lib.oracle_plaquette.argtypes = [P, ctypes.c_int, P]
         lib.oracle_plaquette.restype = ctypes.c_double
+        lib.oracle_clover.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P]
         _lib = lib
     return _lib
 
@@ -186,31 +187,35 @@ def normal_op(U, x_e, m0):
     return dhat_dagger(U, dhat(U, x_e, m0), m0)
 
 
-def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None):
+def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None, op=None):
     """Conjugate gradients for (D^+ D^) x = b on even sites.
 
     Plain Hestenes-Stiefel iteration; stops when the recursively updated
     residual satisfies ||r|| <= tol ||b||, then recomputes the true residual
     b - A x and continues from it if that check fails.  Returns (x, info).
+    `op(x)` replaces D^+ D^ x when given (e.g. the clover operator).
     """
+    if op is None:
+        def op(v):
+            return normal_op(U, v, m0)
     b_e = restrict(_cplx(b_e), 0)
     bnorm = norm(b_e)
     x = np.zeros_like(b_e) if x0 is None else restrict(_cplx(x0), 0)
-    r = b_e - normal_op(U, x, m0) if x0 is not None else b_e.copy()
+    r = b_e - op(x) if x0 is not None else b_e.copy()
     p = r.copy()
     rr = np.real(inner(r, r))
     iters = 0
     t0 = time.perf_counter()
     while iters < maxiter:
         if np.sqrt(rr) <= tol * bnorm:
-            r_true = b_e - normal_op(U, x, m0)
+            r_true = b_e - op(x)
             rr_true = np.real(inner(r_true, r_true))
             if np.sqrt(rr_true) <= tol * bnorm:
                 break
             r = r_true
             p = r.copy()
             rr = rr_true
-        Ap = normal_op(U, p, m0)
+        Ap = op(p)
         alpha = rr / np.real(inner(p, Ap))
         x = x + alpha * p
         r = r - alpha * Ap
@@ -218,7 +223,7 @@ def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None):
         p = r + (rr_new / rr) * p
         rr = rr_new
         iters += 1
-    res = norm(b_e - normal_op(U, x, m0)) / bnorm
+    res = norm(b_e - op(x)) / bnorm
     return x, {"iters": iters, "true_rel_residual": res, "seconds": time.perf_counter() - t0}
 
 
@@ -287,3 +292,71 @@ def action_force(U, phi_e, m0, tol=1e-12, maxiter=10000, real_links=False):
     X, Y = action_force_fields(U, xi, m0)
     m = 4.0 + m0
     return (2.0 / m) * force(X, Y, real_links=real_links), xi, info
+
+
+# ---------------------------------------------------------------------------
+# Clover (Sheikholeslami-Wohlert) term — the paper's Sec. 2.2 diagonal term
+# ---------------------------------------------------------------------------
+
+def clover(U, csw):
+    """A(x) = c_sw (i/4) sum_{mu,nu} sigma_{mu nu} (x) F_{mu nu}(x) for every site;
+    shape [T, L1, L2, L3, 4N, 4N] (row index spin * N + colour).  See oracle.c."""
+    dims = U.shape[1:5]
+    n = U.shape[-1]
+    A = np.empty(tuple(dims) + (4 * n, 4 * n), np.complex128)
+    _load().oracle_clover(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), float(csw), _ptr(A))
+    return A
+
+
+def apply_site_matrix(M, psi):
+    """(M psi)(x) = M(x) psi(x) with M [..., 4N, 4N] and psi [..., 4, N]."""
+    n = psi.shape[-1]
+    flat = psi.reshape(psi.shape[:4] + (4 * n,))
+    return np.einsum("...ij,...j->...i", M, flat).reshape(psi.shape)
+
+
+def dirac_clover(U, psi, m0, csw):
+    """D_sw psi = D psi + A psi."""
+    return dirac(U, psi, m0) + apply_site_matrix(clover(U, csw), psi)
+
+
+def dirac_clover_dagger(U, psi, m0, csw):
+    return apply_gamma5(dirac_clover(U, apply_gamma5(psi), m0, csw))
+
+
+def clover_diag(U, m0, csw):
+    """M(x) = (4 + m0) + A(x), the site-diagonal block of D_sw, and its inverse."""
+    A = clover(U, csw)
+    n4 = A.shape[-1]
+    M = A + (4.0 + m0) * np.eye(n4)
+    return M, np.linalg.inv(M)
+
+
+def dhat_clover(U, psi_e, m0, csw, Mfields=None):
+    """D^ = M_ee - D_eo M_oo^{-1} D_oe on even sites (Schur complement of D_sw)."""
+    M, Minv = clover_diag(U, m0, csw) if Mfields is None else Mfields
+    psi_e = restrict(psi_e, 0)
+    t_o = apply_site_matrix(Minv, hop_block(U, psi_e, 1))
+    t_o = restrict(t_o, 1)
+    return restrict(apply_site_matrix(M, psi_e), 0) - hop_block(U, t_o, 0)
+
+
+def dhat_clover_dagger(U, psi_e, m0, csw, Mfields=None):
+    return apply_gamma5(dhat_clover(U, apply_gamma5(psi_e), m0, csw, Mfields))
+
+
+def cg_clover(U, b_e, m0, csw, tol=1e-10, maxiter=10000):
+    """CG on D^+ D^ for the clover operator."""
+    Mf = clover_diag(U, m0, csw)
+
+    def op(v):
+        return dhat_clover_dagger(U, dhat_clover(U, v, m0, csw, Mf), m0, csw, Mf)
+
+    return cg(U, b_e, m0, tol=tol, maxiter=maxiter, op=op)
+
+
+def true_residual_clover(U, b_e, x_e, m0, csw):
+    Mf = clover_diag(U, m0, csw)
+    b_e = restrict(_cplx(b_e), 0)
+    Ax = dhat_clover_dagger(U, dhat_clover(U, restrict(_cplx(x_e), 0), m0, csw, Mf), m0, csw, Mf)
+    return norm(b_e - Ax) / norm(b_e)

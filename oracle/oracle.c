@@ -288,3 +288,141 @@ double oracle_plaquette(const int *d, int n, const cplx *U)
     }
     return total / (6.0 * V);
 }
+
+/*
+ * Clover (Sheikholeslami-Wohlert) term, Sec. 2.2 of the paper ("another
+ * diagonal term" of the improved operator; the paper gives no formula).
+ * Reading: the standard one,
+ *   A(x) = c_sw (i/4) sum_{mu,nu} sigma_{mu nu} (x) F_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2) [g_mu, g_nu],
+ *   F_{mu nu}(x) = (1/8) [Q_{mu nu}(x) - Q_{mu nu}(x)^+],
+ * with Q_{mu nu}(x) the sum of the four plaquettes of the (mu, nu) plane that
+ * start and end at x, all with the same orientation:
+ *   U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+ *   + U_nu(x) U_mu(x+nu-mu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+ *   + U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+ *   + U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+ .
+ * The links are those of the fermion representation.  The improved operator
+ * is D_sw = D + A.  `A` receives the 4N x 4N matrix of every site,
+ * [V][4N][4N] with row index spin * N + colour.
+ */
+static void matmul(int n, const cplx *a, const cplx *b, cplx *c)
+{
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            cplx z = 0;
+            for (int k = 0; k < n; k++) z += a[i * n + k] * b[k * n + j];
+            c[i * n + j] = z;
+        }
+}
+
+static void dagger_of(int n, const cplx *a, cplx *c)
+{
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) c[i * n + j] = conj(a[j * n + i]);
+}
+
+/* product of four matrices a b c d (n x n) */
+static void prod4(int n, const cplx *a, const cplx *b, const cplx *c, const cplx *d, cplx *out)
+{
+    cplx t1[MAXN * MAXN], t2[MAXN * MAXN];
+    matmul(n, a, b, t1);
+    matmul(n, t1, c, t2);
+    matmul(n, t2, d, out);
+}
+
+static const cplx *link_at(const int *d, int n, const cplx *U, int mu, const int x[4])
+{
+    return U + ((long)mu * volume(d) + lexidx(d, x)) * n * n;
+}
+
+static void shifted(const int *d, const int x[4], int mu, int smu, int nu, int snu, int y[4])
+{
+    memcpy(y, x, 4 * sizeof(int));
+    y[mu] = (y[mu] + smu + d[mu]) % d[mu];
+    y[nu] = (y[nu] + snu + d[nu]) % d[nu];
+}
+
+void oracle_clover(const int *d, int n, const cplx *U, double csw, cplx *A)
+{
+    const long V = volume(d);
+    const int ns = 4 * n;
+    cplx G[4][4][4];
+    for (int mu = 0; mu < 4; mu++) gamma_matrix(mu, G[mu]);
+
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        int x[4];
+        coords(d, s, x);
+        cplx *a = A + s * ns * ns;
+        for (int k = 0; k < ns * ns; k++) a[k] = 0;
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = 0; nu < 4; nu++) {
+                if (mu == nu) continue;
+                cplx Q[MAXN * MAXN], L[MAXN * MAXN], d1[MAXN * MAXN], d2[MAXN * MAXN];
+                for (int k = 0; k < n * n; k++) Q[k] = 0;
+                /* leaf 1 */
+                {
+                    int y1[4], y2[4];
+                    shifted(d, x, mu, 1, nu, 0, y1);
+                    shifted(d, x, mu, 0, nu, 1, y2);
+                    dagger_of(n, link_at(d, n, U, mu, y2), d1);
+                    dagger_of(n, link_at(d, n, U, nu, x), d2);
+                    prod4(n, link_at(d, n, U, mu, x), link_at(d, n, U, nu, y1), d1, d2, L);
+                    for (int k = 0; k < n * n; k++) Q[k] += L[k];
+                }
+                /* leaf 2 */
+                {
+                    int y1[4], y2[4];
+                    shifted(d, x, mu, -1, nu, 1, y1);
+                    shifted(d, x, mu, -1, nu, 0, y2);
+                    cplx d3[MAXN * MAXN];
+                    dagger_of(n, link_at(d, n, U, mu, y1), d1);
+                    dagger_of(n, link_at(d, n, U, nu, y2), d3);
+                    prod4(n, link_at(d, n, U, nu, x), d1, d3, link_at(d, n, U, mu, y2), L);
+                    for (int k = 0; k < n * n; k++) Q[k] += L[k];
+                }
+                /* leaf 3 */
+                {
+                    int y1[4], y2[4], y3[4];
+                    shifted(d, x, mu, -1, nu, 0, y1);
+                    shifted(d, x, mu, -1, nu, -1, y2);
+                    shifted(d, x, mu, 0, nu, -1, y3);
+                    cplx d3[MAXN * MAXN];
+                    dagger_of(n, link_at(d, n, U, mu, y1), d1);
+                    dagger_of(n, link_at(d, n, U, nu, y2), d3);
+                    prod4(n, d1, d3, link_at(d, n, U, mu, y2), link_at(d, n, U, nu, y3), L);
+                    for (int k = 0; k < n * n; k++) Q[k] += L[k];
+                }
+                /* leaf 4 */
+                {
+                    int y1[4], y2[4];
+                    shifted(d, x, mu, 0, nu, -1, y1);
+                    shifted(d, x, mu, 1, nu, -1, y2);
+                    cplx d3[MAXN * MAXN];
+                    dagger_of(n, link_at(d, n, U, nu, y1), d1);
+                    dagger_of(n, link_at(d, n, U, mu, x), d3);
+                    prod4(n, d1, link_at(d, n, U, mu, y1), link_at(d, n, U, nu, y2), d3, L);
+                    for (int k = 0; k < n * n; k++) Q[k] += L[k];
+                }
+                /* F = (Q - Q^+) / 8 */
+                cplx F[MAXN * MAXN];
+                for (int i = 0; i < n; i++)
+                    for (int j = 0; j < n; j++) F[i * n + j] = (Q[i * n + j] - conj(Q[j * n + i])) / 8.0;
+                /* sigma_{mu nu} = (i/2)(g_mu g_nu - g_nu g_mu) */
+                cplx sig[4][4];
+                for (int a1 = 0; a1 < 4; a1++)
+                    for (int b1 = 0; b1 < 4; b1++) {
+                        cplx z = 0;
+                        for (int k = 0; k < 4; k++) z += G[mu][a1][k] * G[nu][k][b1] - G[nu][a1][k] * G[mu][k][b1];
+                        sig[a1][b1] = 0.5 * I * z;
+                    }
+                /* A += c_sw (i/4) sigma (x) F */
+                for (int a1 = 0; a1 < 4; a1++)
+                    for (int b1 = 0; b1 < 4; b1++)
+                        for (int i = 0; i < n; i++)
+                            for (int j = 0; j < n; j++)
+                                a[(a1 * n + i) * ns + (b1 * n + j)] += csw * 0.25 * I * sig[a1][b1] * F[i * n + j];
+            }
+    }
+}

@@ -29,8 +29,13 @@
 #ifndef HRD_SLAB
 #define HRD_SLAB 0
 #endif
+#ifndef HRD_HOP_BLOCK
+#define HRD_HOP_BLOCK 256
+#endif
 
 namespace hrd {
+
+constexpr int kHopBlock = HRD_HOP_BLOCK;  // threads per workgroup of the hopping kernel
 
 // Widest x1-slab whose t-slice holds at most kSlabSites = 6 * 48 * 48 / 2
 // sites per parity (the best of the widths measured on 48^4, where one FP64
@@ -100,7 +105,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 // parities in one launch (blocks alternate parity), NORM writes one partial
 // of ||out||^2 per block.
 template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false>
-__global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
 {
     constexpr int N = NCol<REP>::value;
     constexpr int NC = 4 * N;
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
         self = a.self;
         dst = a.dst;
     }
-    const int w = lb * kBlock + threadIdx.x;
+    const int w = lb * kHopBlock + threadIdx.x;
     double nrm = 0;
     if (w < g.Vh) {
         int idx;
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(kBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
         }
     }
     if constexpr (NORM) {
-        const double t = block_sum<kBlock>(nrm);
+        const double t = block_sum<kHopBlock>(nrm);
         if (threadIdx.x == 0) a.partials[part_idx] = t;
     }
 }
@@ -177,7 +182,7 @@ template <int REP, typename R>
 hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
 {
     const int nb = hop_blocks(a.g) * (full ? 2 : 1);
-    const dim3 grid(nb), block(kBlock);
+    const dim3 grid(nb), block(kHopBlock);
 #define HRD_LAUNCH(D, A, NR, F) hipLaunchKernelGGL((hop_kernel<REP, R, D, A, NR, F>), grid, block, 0, st, a)
     if (full) {
         if (dag)
@@ -208,14 +213,14 @@ hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool 
 template <int REP, typename R>
 hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)), dim3(kBlock), 0,
+    hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)), dim3(kHopBlock), 0,
                        st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int hop_blocks(const Geom &g) { return (g.Vh + kBlock - 1) / kBlock; }
+int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st)
 {

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void force_kernel(Geom g, const char *X, co
 
 hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, void *F, double scale, hipStream_t st)
 {
-    const dim3 grid(2 * hop_blocks(g)), block(kBlock);
+    const dim3 grid(2 * ((g.Vh + kBlock - 1) / kBlock)), block(kBlock);
     const char *x = reinterpret_cast<const char *>(X);
     const char *y = reinterpret_cast<const char *>(Y);
     if (base_rep(rep) == HRD_FUND) hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale);
