@@ -281,6 +281,71 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
                         void *work, size_t work_bytes, hrd_cg_info *info, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Clover (Sheikholeslami-Wohlert) improvement: Sec. 2.2 adds to the Wilson
+   operator a term diagonal in the sites and precomputes the fields it needs
+   once per gauge field.  The paper gives no formula; the standard one is
+     A(x) = c_sw (i/4) sum_{mu != nu} sigma_{mu nu} (x) F_{mu nu}(x),
+     sigma_{mu nu} = (i/2) [g_mu, g_nu],  F_{mu nu} = (Q_{mu nu} - Q_{mu nu}^+)/8,
+   Q_{mu nu}(x) the sum of the four same-oriented plaquettes of the (mu, nu)
+   plane at x, in the links of the fermion representation, and
+     D_sw = M - H/2 with the site matrix M(x) = m + A(x),
+     D^_sw = M_ee - D_eo M_oo^{-1} D_oe on even sites,  D^_sw^+ = g5 D^_sw g5.
+   M is Hermitian and commutes with g5: two Hermitian 2N x 2N blocks per site
+   (spins 0,1 and spins 2,3; row (spin mod 2) N + colour).
+   PACKED CLOVER FIELD (M or M^{-1}, one precision): per site and block the
+   2N real diagonal entries, then the N(2N-1) complex entries below the
+   diagonal in row order ((i, j), i > j, at i(i-1)/2 + j) as (re, im): 4N^2
+   reals per block, 8N^2 per site, upper block first.  The field is
+   [parity][planes][Vh] with planes of 16-byte elements holding consecutive
+   reals (2 float64 or 4 float32).  NATURAL clover layout (hrd_unpack_clover):
+   complex128 [V][4N][4N], row and column index spin * N + colour.         */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of one packed clover field (M or M^{-1}) of the given precision. */
+size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec);
+
+/* Builds M = (4 + m0) + A and M^{-1} (each block inverted by Gauss-Jordan
+   elimination with partial pivoting) in FP64 from the packed FP64 gauge
+   field U64 of rep.  M64 and Minv64 receive hrd_clover_bytes(F64) bytes each.
+   A block that is singular yields non-finite entries (no error is raised:
+   M is not inspected on the host).  Asynchronous. */
+hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, const void *U64,
+                            double csw, double m0, void *M64, void *Minv64, void *stream);
+
+/* FP64 -> FP32 copy of a packed clover field (for the mixed-precision CG
+   and FP32 operators).  Asynchronous. */
+hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64,
+                              void *C32, void *stream);
+
+/* Packed FP64 clover field -> natural layout (complex128 [V][4N][4N], both
+   blocks and the zero off-diagonal chirality blocks written out).
+   Asynchronous. */
+hrd_status hrd_unpack_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64,
+                             void *C_nat, void *stream);
+
+/* out = D_sw psi (HRD_FULL, full-lattice fields) or out_e = D^_sw psi_e
+   (HRD_EO, even half fields; needs Minv and a workspace of
+   hrd_dirac_workspace_bytes(HRD_EO) bytes); dagger != 0 applies the adjoint.
+   U, M, Minv, psi and out share the precision prec.  The off-diagonal blocks
+   D_eo, D_oe carry no clover term: apply them with hrd_dirac_apply
+   (HRD_HOP_EO, HRD_HOP_OE gives HRD_EINVAL here).  The mass is the one built
+   into M.  Asynchronous. */
+hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                                  const void *U, const void *M, const void *Minv,
+                                  const void *psi, void *out, hrd_parity parity,
+                                  int dagger, void *work, void *stream);
+
+/* CG on A = D^_sw^+ D^_sw, as hrd_cg_solve (same workspace size, same modes,
+   tolerance, reliable updates, info and errors), with the FP64 clover fields
+   M64, Minv64 and, for HRD_CG_MIXED, their FP32 copies M32, Minv32
+   (ignored for HRD_CG_F64). */
+hrd_status hrd_cg_solve_clover(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
+                               const void *U64, const void *U32, const void *M64,
+                               const void *Minv64, const void *M32, const void *Minv32,
+                               const void *b, void *x, double tol, int maxiter, double delta,
+                               void *work, size_t work_bytes, hrd_cg_info *info, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Fermion force for the HMC (Sec. 2.1 mentions the HMC the even/odd operator
    serves).                                                                  */
 /* ------------------------------------------------------------------------ */

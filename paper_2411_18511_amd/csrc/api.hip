@@ -10,6 +10,7 @@
 #include <string>
 
 #include "api_util.h"
+#include "clover.h"
 #include "kernels.h"
 
 namespace hrd {
@@ -74,9 +75,15 @@ size_t gauge_bytes(const hrd_lattice *lat, int rep, int prec)
 
 int ncomp_of(int rep) { return 4 * ncolour(rep); }
 
+size_t clover_bytes(const hrd_lattice *lat, int rep, int prec)
+{
+    const long long V = (long long)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    return (size_t)V * clover_site_reals(ncolour(rep)) * (prec == HRD_F64 ? 8 : 4);
+}
+
 // D^ in (even half) -> out (even half), tmp: odd half of the same precision.
 hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, void *tmp,
-                      double m0, bool dag, double *norm_partials, hipStream_t st)
+                      double m0, bool dag, double *norm_partials, hipStream_t st, const CloverRef *cl)
 {
     const double m = 4.0 + m0;
     HopArgs a{};
@@ -88,20 +95,24 @@ hipError_t apply_dhat(int rep, int prec, const Geom &g, const void *U, const voi
     a.a = 0.0;
     a.b = -0.5;
     a.parity = 1;
-    hipError_t e = launch_hop(rep, prec, a, dag, false, false, false, st);
+    // tmp = D_oe in, or M_oo^{-1} D_oe in
+    if (cl) a.clov = cl->Minv;
+    hipError_t e = launch_hop(rep, prec, a, dag, false, false, false, st, cl ? CLOV_INV : CLOV_NONE);
     if (e != hipSuccess) return e;
+    // out = m in - (1/m) D_eo tmp, or M_ee in - D_eo tmp
     a.src = (const char *)tmp;
     a.self = (const char *)in;
     a.dst = (char *)out;
     a.a = m;
-    a.b = 0.5 / m;
+    a.b = cl ? 0.5 : 0.5 / m;
     a.parity = 0;
     a.partials = norm_partials;
-    return launch_hop(rep, prec, a, dag, true, norm_partials != nullptr, false, st);
+    if (cl) a.clov = cl->M;
+    return launch_hop(rep, prec, a, dag, true, norm_partials != nullptr, false, st, cl ? CLOV_SELF : CLOV_NONE);
 }
 
 hipError_t apply_dhat_dag_update_r(int rep, int prec, const Geom &g, const void *U, const void *q, void *r, void *tmp,
-                                   double m0, const double *sc, double *partials, hipStream_t st)
+                                   double m0, const double *sc, double *partials, hipStream_t st, const CloverRef *cl)
 {
     const double m = 4.0 + m0;
     HopArgs a{};
@@ -112,18 +123,20 @@ hipError_t apply_dhat_dag_update_r(int rep, int prec, const Geom &g, const void 
     a.a = 0.0;
     a.b = -0.5;
     a.parity = 1;
-    hipError_t e = launch_hop(rep, prec, a, true, false, false, false, st);
+    if (cl) a.clov = cl->Minv;
+    hipError_t e = launch_hop(rep, prec, a, true, false, false, false, st, cl ? CLOV_INV : CLOV_NONE);
     if (e != hipSuccess) return e;
     a.src = (const char *)tmp;
     a.self = (const char *)q;
     a.dst = nullptr;
     a.a = m;
-    a.b = 0.5 / m;
+    a.b = cl ? 0.5 : 0.5 / m;
     a.parity = 0;
     a.partials = partials;
     a.r = r;
     a.sc = sc;
-    return launch_hop_rupdate(rep, prec, a, st);
+    if (cl) a.clov = cl->M;
+    return launch_hop_rupdate(rep, prec, a, st, cl ? CLOV_SELF : CLOV_NONE);
 }
 
 hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, const void *in, void *out,
@@ -141,7 +154,7 @@ hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, cons
 }
 
 hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, double m0,
-                      bool dag, hipStream_t st)
+                      bool dag, hipStream_t st, const CloverRef *cl)
 {
     HopArgs a{};
     a.g = g;
@@ -151,7 +164,8 @@ hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const voi
     a.a = 4.0 + m0;
     a.b = -0.5;
     a.half_bytes = (size_t)g.Vh * spinor_site_bytes(rep, prec);
-    return launch_hop(rep, prec, a, dag, true, false, true, st);
+    if (cl) a.clov = cl->M;
+    return launch_hop(rep, prec, a, dag, true, false, true, st, cl ? CLOV_SELF : CLOV_NONE);
 }
 
 }  // namespace hrd
@@ -377,6 +391,82 @@ hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
     return check_hip(e, "dirac_apply launch");
 }
 
+size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
+{
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    return clover_bytes(lat, rep, prec);
+}
+
+hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, const void *U64, double csw, double m0, void *M64,
+                            void *Minv64, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (!U64 || !M64 || !Minv64) return fail(HRD_EINVAL, "NULL field pointer");
+    if (!std::isfinite(csw) || !std::isfinite(m0)) return fail(HRD_EINVAL, "csw and m0 must be finite");
+    const size_t cb = clover_bytes(lat, rep, HRD_F64);
+    const size_t ub = gauge_bytes(lat, rep, HRD_F64);
+    if (overlap(M64, cb, Minv64, cb) || overlap(M64, cb, U64, ub) || overlap(Minv64, cb, U64, ub))
+        return fail(HRD_EALIAS, "clover outputs overlap each other or the gauge field");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_clover_build(rep, g, U64, csw, 4.0 + m0, M64, Minv64, (hipStream_t)stream),
+                     "clover_build launch");
+}
+
+hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C32, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (!C64 || !C32) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(C64, clover_bytes(lat, rep, HRD_F64), C32, clover_bytes(lat, rep, HRD_F32)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_convert_clover(rep, g, C64, C32, (hipStream_t)stream), "convert_clover launch");
+}
+
+hrd_status hrd_unpack_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C_nat, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (!C64 || !C_nat) return fail(HRD_EINVAL, "NULL field pointer");
+    const size_t cb = clover_bytes(lat, rep, HRD_F64);
+    if (overlap(C64, cb, C_nat, 4 * cb)) return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_unpack_clover(rep, g, C64, C_nat, (hipStream_t)stream), "unpack_clover launch");
+}
+
+hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *M,
+                                  const void *Minv, const void *psi, void *out, hrd_parity parity, int dagger,
+                                  void *work, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec(rep, prec));
+    if (parity != HRD_FULL && parity != HRD_EO)
+        return fail(HRD_EINVAL, "clover operator supports HRD_FULL and HRD_EO (hop blocks are those of hrd_dirac_apply)");
+    if (!U || !M || !psi || !out) return fail(HRD_EINVAL, "NULL field pointer");
+    if (parity == HRD_EO && !Minv) return fail(HRD_EINVAL, "HRD_EO needs the inverse clover field");
+    const int np = parity == HRD_FULL ? 2 : 1;
+    const size_t sb = spinor_bytes(lat, rep, prec, np);
+    const size_t ub = gauge_bytes(lat, rep, prec);
+    const size_t cb = clover_bytes(lat, rep, prec);
+    if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub) || overlap(out, sb, M, cb) ||
+        overlap(out, sb, Minv, cb))
+        return fail(HRD_EALIAS, "output overlaps an input");
+    if (parity == HRD_EO) {
+        if (!work) return fail(HRD_EINVAL, "HRD_EO needs a workspace of hrd_dirac_workspace_bytes bytes");
+        const size_t wb = spinor_bytes(lat, rep, prec, 1);
+        if (overlap(work, wb, psi, sb) || overlap(work, wb, out, sb) || overlap(work, wb, U, ub) ||
+            overlap(work, wb, M, cb) || overlap(work, wb, Minv, cb))
+            return fail(HRD_EALIAS, "workspace overlaps a field");
+    }
+    const Geom g = make_geom(lat->dims);
+    const hipStream_t st = (hipStream_t)stream;
+    const CloverRef cl{M, Minv};
+    hipError_t e = parity == HRD_FULL ? apply_full(rep, prec, g, U, psi, out, 0.0, dagger != 0, st, &cl)
+                                      : apply_dhat(rep, prec, g, U, psi, out, work, 0.0, dagger != 0, nullptr, st, &cl);
+    return check_hip(e, "dirac_apply_clover launch");
+}
+
 size_t hrd_blas_workspace_bytes(void) { return sizeof(double) * (2 * kRedBlocks + 8); }
 
 static hrd_status blas_common(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity, void *work)
@@ -457,9 +547,11 @@ size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode m
     return carve_cg(lat, rep, mode, nullptr, nullptr);
 }
 
-hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, const void *U64, const void *U32,
-                        const void *b, void *x, double m0, double tol, int maxiter, double delta, void *work,
-                        size_t work_bytes, hrd_cg_info *info, void *stream)
+// CG on D^+ D^ x = b (Wilson, or clover when cl64 is given; the mixed mode
+// then also needs cl32).
+static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, const void *U64, const void *U32,
+                         const CloverRef *cl64, const CloverRef *cl32, const void *b, void *x, double m0, double tol,
+                         int maxiter, double delta, void *work, size_t work_bytes, hrd_cg_info *info, void *stream)
 {
     const auto t0 = std::chrono::steady_clock::now();
     hrd_cg_info inf{};
@@ -476,7 +568,10 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED) return finish(fail(HRD_EINVAL, "invalid CG mode %d", (int)mode));
     if (!U64 || !b || !x || !work) return finish(fail(HRD_EINVAL, "NULL pointer"));
     if (mode == HRD_CG_MIXED && !U32) return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 gauge field"));
-    if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
+    if (!cl64 && (!std::isfinite(m0) || 4.0 + m0 == 0.0)) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
+    if (cl64 && (!cl64->M || !cl64->Minv)) return finish(fail(HRD_EINVAL, "NULL FP64 clover field"));
+    if (cl64 && mode == HRD_CG_MIXED && (!cl32 || !cl32->M || !cl32->Minv))
+        return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 clover fields"));
     if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(HRD_EINVAL, "tol must be positive"));
     if (maxiter < 0) return finish(fail(HRD_EINVAL, "maxiter must be >= 0"));
     const size_t need = carve_cg(lat, rep, mode, nullptr, nullptr);
@@ -486,6 +581,15 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     if (overlap(work, need, x, h64) || overlap(work, need, b, h64) ||
         overlap(work, need, U64, gauge_bytes(lat, rep, HRD_F64)))
         return finish(fail(HRD_EALIAS, "workspace overlaps a field"));
+    if (cl64) {
+        const size_t c64 = clover_bytes(lat, rep, HRD_F64), c32 = clover_bytes(lat, rep, HRD_F32);
+        bool bad = overlap(work, need, cl64->M, c64) || overlap(work, need, cl64->Minv, c64) ||
+                   overlap(x, h64, cl64->M, c64) || overlap(x, h64, cl64->Minv, c64);
+        if (mode == HRD_CG_MIXED)
+            bad = bad || overlap(work, need, cl32->M, c32) || overlap(work, need, cl32->Minv, c32) ||
+                  overlap(x, h64, cl32->M, c32) || overlap(x, h64, cl32->Minv, c32);
+        if (bad) return finish(fail(HRD_EALIAS, "a clover field overlaps x or the workspace"));
+    }
     if (delta <= 0.0) delta = 0.1;
 
     CgBuffers w;
@@ -524,8 +628,8 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
 
     // r = b - A x (FP64), rr = ||r||^2
     auto true_residual = [&](void) -> hrd_status {
-        hipError_t e = apply_dhat(rep, HRD_F64, g, U64, x, w.q64, w.t64, m0, false, nullptr, st);
-        if (e == hipSuccess) e = apply_dhat(rep, HRD_F64, g, U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st);
+        hipError_t e = apply_dhat(rep, HRD_F64, g, U64, x, w.q64, w.t64, m0, false, nullptr, st, cl64);
+        if (e == hipSuccess) e = apply_dhat(rep, HRD_F64, g, U64, w.q64, w.Ap64, w.t64, m0, true, nullptr, st, cl64);
         if (e == hipSuccess) {
             if (mode == HRD_CG_F64) e = launch_cg_residual64(n64, b, w.Ap64, w.r64, w.partials, st);
             else e = launch_cg_residual_mixed(g.Vh, nc, b, w.Ap64, w.r64, w.r32, w.partials, st);
@@ -549,9 +653,9 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     if (mode == HRD_CG_F64) {
         CG_HIP(launch_copy(h64, w.r64, w.p64, st), "copy");
         while (inf.iters < maxiter) {
-            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st), "D^ p");
+            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st, cl64), "D^ p");
             CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
-            CG_HIP(apply_dhat_dag_update_r(rep, HRD_F64, g, U64, w.q64, w.r64, w.t64, m0, w.sc, w.partials, st),
+            CG_HIP(apply_dhat_dag_update_r(rep, HRD_F64, g, U64, w.q64, w.r64, w.t64, m0, w.sc, w.partials, st, cl64),
                    "r -= alpha D^+ q");
             CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
             CG_HIP(launch_cg_update_xp64(n64, x, w.p64, w.r64, w.sc, st), "update x, p");
@@ -587,9 +691,9 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     CG_HIP(launch_copy(h32, w.r32, w.p32, st), "copy");
     double rmax = std::sqrt(rr);
     while (inf.iters < maxiter) {
-        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.p32, w.q32, w.t32, m0, false, w.partials, st), "D^ p");
+        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.p32, w.q32, w.t32, m0, false, w.partials, st, cl32), "D^ p");
         CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
-        CG_HIP(apply_dhat_dag_update_r(rep, HRD_F32, g, U32, w.q32, w.r32, w.t32, m0, w.sc, w.partials, st),
+        CG_HIP(apply_dhat_dag_update_r(rep, HRD_F32, g, U32, w.q32, w.r32, w.t32, m0, w.sc, w.partials, st, cl32),
                "r -= alpha D^+ q");
         CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
         inf.iters++;
@@ -627,6 +731,24 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, c
     return finish(fail(HRD_ENOCONV, "mixed CG did not converge in %d iterations (residual %g)", maxiter,
                        inf.true_rel_residual));
 #undef CG_HIP
+}
+
+hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, const void *U64, const void *U32,
+                        const void *b, void *x, double m0, double tol, int maxiter, double delta, void *work,
+                        size_t work_bytes, hrd_cg_info *info, void *stream)
+{
+    return cg_run(lat, rep, mode, U64, U32, nullptr, nullptr, b, x, m0, tol, maxiter, delta, work, work_bytes, info,
+                  stream);
+}
+
+hrd_status hrd_cg_solve_clover(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, const void *U64,
+                               const void *U32, const void *M64, const void *Minv64, const void *M32,
+                               const void *Minv32, const void *b, void *x, double tol, int maxiter, double delta,
+                               void *work, size_t work_bytes, hrd_cg_info *info, void *stream)
+{
+    const CloverRef c64{M64, Minv64}, c32{M32, Minv32};
+    return cg_run(lat, rep, mode, U64, U32, &c64, &c32, b, x, 0.0, tol, maxiter, delta, work, work_bytes, info,
+                  stream);
 }
 
 hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *X,

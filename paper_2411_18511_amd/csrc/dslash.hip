@@ -2,7 +2,8 @@
 // paper's Sec. 2.1, here covering the whole single-GPU lattice), with fused
 // epilogues for the plain operator D = m - H/2, the off-diagonal blocks
 // D_eo = -H_eo/2 and the second stage of the even/odd operator
-// D^ = m - (1/m) D_eo D_oe.
+// D^ = m - (1/m) D_eo D_oe, and the clover variants (site matrix M = m + A
+// in place of m: D = M - H/2, D^ = M_ee - D_eo M_oo^{-1} D_oe).
 //
 // One thread per target site.  For each of the 8 directions the neighbour
 // spinor (opposite parity) is spin-projected to a half spinor with
@@ -10,6 +11,7 @@
 // components are reconstructed from the upper two (the projector has rank 2).
 // Every link is read exactly once per hop; the sign s_mu(x) of the
 // time-antiperiodic boundary is applied to the half spinor.
+#include "clover.h"
 #include "kernels.h"
 #include "spin.h"
 
@@ -103,8 +105,8 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 
 // out = a psi_self(x) + b (H psi_src)(x) on the target parity; FULL runs both
 // parities in one launch (blocks alternate parity), NORM writes one partial
-// of ||out||^2 per block.
-template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false>
+// of ||out||^2 per block.  CLOV selects a clover epilogue (CloverMode).
+template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE>
 __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
 {
     constexpr int N = NCol<REP>::value;
@@ -142,7 +144,19 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
         hop_dir<3, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
         const R cb = (R)a.b;
         Cx<R> out[NC];
-        if constexpr (HAS_A) {
+        if constexpr (CLOV == CLOV_INV) {
+            Cx<R> t[NC];
+#pragma unroll
+            for (int k = 0; k < NC; k++) t[k] = cb * acc[k];
+            clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, t, out);
+        } else if constexpr (HAS_A && CLOV == CLOV_SELF) {
+            Cx<R> self_v[NC], ms[NC];
+            SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
+            clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, self_v, ms);
+#pragma unroll
+            for (int k = 0; k < NC; k++)
+                out[k] = Cx<R>{fmadd(cb, acc[k].re, ms[k].re), fmadd(cb, acc[k].im, ms[k].im)};
+        } else if constexpr (HAS_A) {
             const R ca = (R)a.a;
             Cx<R> self_v[NC];
             SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
@@ -178,13 +192,29 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
     }
 }
 
-template <int REP, typename R>
+template <int REP, typename R, int CLOV>
 hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
 {
     const int nb = hop_blocks(a.g) * (full ? 2 : 1);
     const dim3 grid(nb), block(kHopBlock);
-#define HRD_LAUNCH(D, A, NR, F) hipLaunchKernelGGL((hop_kernel<REP, R, D, A, NR, F>), grid, block, 0, st, a)
-    if (full) {
+#define HRD_LAUNCH(D, A, NR, F) \
+    hipLaunchKernelGGL((hop_kernel<REP, R, D, A, NR, F, false, CLOV>), grid, block, 0, st, a)
+    if constexpr (CLOV == CLOV_INV) {
+        // M^{-1} (b H src): no self term, no norm
+        if (dag) HRD_LAUNCH(true, false, false, false);
+        else HRD_LAUNCH(false, false, false, false);
+    } else if constexpr (CLOV == CLOV_SELF) {
+        if (full) {
+            if (dag) HRD_LAUNCH(true, true, false, true);
+            else HRD_LAUNCH(false, true, false, true);
+        } else if (dag) {
+            if (norm) HRD_LAUNCH(true, true, true, false);
+            else HRD_LAUNCH(true, true, false, false);
+        } else {
+            if (norm) HRD_LAUNCH(false, true, true, false);
+            else HRD_LAUNCH(false, true, false, false);
+        }
+    } else if (full) {
         if (dag)
             HRD_LAUNCH(true, true, false, true);
         else
@@ -211,10 +241,24 @@ hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool 
 }
 
 template <int REP, typename R>
-hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st)
+hipError_t dispatch_hop_clov(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st, int clov)
 {
-    hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)), dim3(kHopBlock), 0,
-                       st, a);
+    switch (clov) {
+        case CLOV_SELF: return dispatch_hop<REP, R, CLOV_SELF>(a, dag, has_a, norm, full, st);
+        case CLOV_INV: return dispatch_hop<REP, R, CLOV_INV>(a, dag, has_a, norm, full, st);
+        default: return dispatch_hop<REP, R, CLOV_NONE>(a, dag, has_a, norm, full, st);
+    }
+}
+
+template <int REP, typename R>
+hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st, int clov)
+{
+    if (clov == CLOV_SELF)
+        hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true, CLOV_SELF>), dim3(hop_blocks(a.g)),
+                           dim3(kHopBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)),
+                           dim3(kHopBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -222,35 +266,39 @@ hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st)
 
 int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
-hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st)
-{
-    const bool d = prec == HRD_F64;
-    switch (rep) {
-        case HRD_FUND: return d ? dispatch_rupd<HRD_FUND, double>(a, st) : dispatch_rupd<HRD_FUND, float>(a, st);
-        case HRD_ADJ: return d ? dispatch_rupd<HRD_ADJ, double>(a, st) : dispatch_rupd<HRD_ADJ, float>(a, st);
-        case HRD_FUND_SU2:
-            return d ? dispatch_rupd<HRD_FUND_SU2, double>(a, st) : dispatch_rupd<HRD_FUND_SU2, float>(a, st);
-        default: return d ? dispatch_rupd<HRD_ADJ_SU2, double>(a, st) : dispatch_rupd<HRD_ADJ_SU2, float>(a, st);
-    }
-}
-
-hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
-                      hipStream_t st)
+hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov)
 {
     const bool d = prec == HRD_F64;
     switch (rep) {
         case HRD_FUND:
-            return d ? dispatch_hop<HRD_FUND, double>(a, dag, has_a, norm, full, st)
-                     : dispatch_hop<HRD_FUND, float>(a, dag, has_a, norm, full, st);
+            return d ? dispatch_rupd<HRD_FUND, double>(a, st, clov) : dispatch_rupd<HRD_FUND, float>(a, st, clov);
         case HRD_ADJ:
-            return d ? dispatch_hop<HRD_ADJ, double>(a, dag, has_a, norm, full, st)
-                     : dispatch_hop<HRD_ADJ, float>(a, dag, has_a, norm, full, st);
+            return d ? dispatch_rupd<HRD_ADJ, double>(a, st, clov) : dispatch_rupd<HRD_ADJ, float>(a, st, clov);
         case HRD_FUND_SU2:
-            return d ? dispatch_hop<HRD_FUND_SU2, double>(a, dag, has_a, norm, full, st)
-                     : dispatch_hop<HRD_FUND_SU2, float>(a, dag, has_a, norm, full, st);
+            return d ? dispatch_rupd<HRD_FUND_SU2, double>(a, st, clov)
+                     : dispatch_rupd<HRD_FUND_SU2, float>(a, st, clov);
         default:
-            return d ? dispatch_hop<HRD_ADJ_SU2, double>(a, dag, has_a, norm, full, st)
-                     : dispatch_hop<HRD_ADJ_SU2, float>(a, dag, has_a, norm, full, st);
+            return d ? dispatch_rupd<HRD_ADJ_SU2, double>(a, st, clov) : dispatch_rupd<HRD_ADJ_SU2, float>(a, st, clov);
+    }
+}
+
+hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
+                      hipStream_t st, int clov)
+{
+    const bool d = prec == HRD_F64;
+    switch (rep) {
+        case HRD_FUND:
+            return d ? dispatch_hop_clov<HRD_FUND, double>(a, dag, has_a, norm, full, st, clov)
+                     : dispatch_hop_clov<HRD_FUND, float>(a, dag, has_a, norm, full, st, clov);
+        case HRD_ADJ:
+            return d ? dispatch_hop_clov<HRD_ADJ, double>(a, dag, has_a, norm, full, st, clov)
+                     : dispatch_hop_clov<HRD_ADJ, float>(a, dag, has_a, norm, full, st, clov);
+        case HRD_FUND_SU2:
+            return d ? dispatch_hop_clov<HRD_FUND_SU2, double>(a, dag, has_a, norm, full, st, clov)
+                     : dispatch_hop_clov<HRD_FUND_SU2, float>(a, dag, has_a, norm, full, st, clov);
+        default:
+            return d ? dispatch_hop_clov<HRD_ADJ_SU2, double>(a, dag, has_a, norm, full, st, clov)
+                     : dispatch_hop_clov<HRD_ADJ_SU2, float>(a, dag, has_a, norm, full, st, clov);
     }
 }
 

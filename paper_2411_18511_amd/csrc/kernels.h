@@ -19,15 +19,22 @@ struct HopArgs {
     size_t half_bytes;  // FULL: bytes of one parity block of a spinor
     void *r;            // RUPD: residual updated in place, r <- r - alpha * out
     const double *sc;   // RUPD: device scalars (alpha in slot S_ALPHA)
+    const void *clov;   // clover epilogues: packed site matrices of the target parity's field
 };
+
+// Clover epilogues of the hopping kernel (the site matrix M = m + A is read
+// from HopArgs::clov, precision of the launch):
+//   CLOV_SELF:  out = M self + b (H src)          (replaces a * self)
+//   CLOV_INV:   out = M (b (H src))               (clov holds M^{-1})
+enum CloverMode { CLOV_NONE = 0, CLOV_SELF = 1, CLOV_INV = 2 };
 
 int hop_blocks(const Geom &g);
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
-                      hipStream_t st);
+                      hipStream_t st, int clov = CLOV_NONE);
 // Second stage of D^+ fused with the CG residual update: out = a self + b H src
 // is not stored; instead r <- r - alpha out and ||r||^2 partials are written
 // (one per block, hop_blocks(g) of them).
-hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st);
+hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov = CLOV_NONE);
 
 // ----- field preparation (pack.hip) ----------------------------------------
 hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,
@@ -96,6 +103,14 @@ hipError_t launch_cg_residual64(size_t n, const void *b, const void *Ax, void *r
 hipError_t launch_copy(size_t bytes, const void *src, void *dst, hipStream_t st);
 // dst = 0
 hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st);
+
+// ----- clover term (clover.hip) ---------------------------------------------
+// M = m + A and M^{-1} of every site from the F64 links of the representation.
+hipError_t launch_clover_build(int rep, const Geom &g, const void *U, double csw, double m, void *M, void *Minv,
+                               hipStream_t st);
+hipError_t launch_convert_clover(int rep, const Geom &g, const void *C64, void *C32, hipStream_t st);
+// packed F64 -> complex128 [V][4N][4N], lexicographic sites
+hipError_t launch_unpack_clover(int rep, const Geom &g, const void *C, void *nat, hipStream_t st);
 
 // ----- force (force.hip) ---------------------------------------------------
 hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, void *F, double scale,

@@ -114,6 +114,13 @@ _sig("hrd_blas_axpy", _I, _LP, _I, _I, _I, _D, _D, _P, _P, ctypes.POINTER(_D), _
 _sig("hrd_blas_xpay", _I, _LP, _I, _I, _I, _P, _D, _D, _P, _P)
 _sig("hrd_cg_workspace_bytes", _S, _LP, _I, _I)
 _sig("hrd_cg_solve", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _D, _I, _D, _P, _S, ctypes.POINTER(CgInfo), _P)
+_sig("hrd_clover_bytes", _S, _LP, _I, _I)
+_sig("hrd_clover_build", _I, _LP, _I, _P, _D, _D, _P, _P, _P)
+_sig("hrd_convert_clover", _I, _LP, _I, _P, _P, _P)
+_sig("hrd_unpack_clover", _I, _LP, _I, _P, _P, _P)
+_sig("hrd_dirac_apply_clover", _I, _LP, _I, _I, _P, _P, _P, _P, _P, _I, _I, _P, _P)
+_sig("hrd_cg_solve_clover", _I, _LP, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _D, _P, _S,
+     ctypes.POINTER(CgInfo), _P)
 _sig("hrd_dirac_force", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _P)
 _sig("hrd_action_force_workspace_bytes", _S, _LP, _I)
 _sig("hrd_action_force", _I, _LP, _I, _P, _P, _P, _D, _D, _P, _S, _P)
@@ -399,6 +406,124 @@ def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=
     info = CgInfo()
     st = _lib.hrd_cg_solve(ctypes.byref(lattice(dims)), rep, mode, _ptr(U64), _ptr(U32), _ptr(b), _ptr(x), float(m0),
                            float(tol), int(maxiter), float(delta), _ptr(work), wb, ctypes.byref(info), _stream())
+    _check(st, allow=(ENOCONV,) if allow_noconv else ())
+    d = info.as_dict()
+    d["status"] = _STATUS_NAMES[st]
+    return x, d
+
+
+# ---------------------------------------------------------------------------
+# clover term
+# ---------------------------------------------------------------------------
+
+def clover_bytes(dims, rep, prec):
+    return _lib.hrd_clover_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _PRECS[prec])
+
+
+@dataclass
+class Clover:
+    """Packed clover fields M = m + A and M^{-1} of one precision."""
+    M: torch.Tensor
+    Minv: torch.Tensor
+    prec: int
+
+
+def clover_build(U64, csw, m0, dims, rep):
+    """FP64 M = (4 + m0) + A and M^{-1} from the packed FP64 gauge field."""
+    rep = _REPS[rep]
+    nb = clover_bytes(dims, rep, F64)
+    _need(U64, gauge_bytes(dims, rep, F64), "U64")
+    M, Minv = _empty(nb, U64.device), _empty(nb, U64.device)
+    _check(_lib.hrd_clover_build(ctypes.byref(lattice(dims)), rep, _ptr(U64), float(csw), float(m0), _ptr(M),
+                                 _ptr(Minv), _stream()))
+    return Clover(M, Minv, F64)
+
+
+def convert_clover(c64, dims, rep):
+    """FP32 copy of an FP64 Clover pair."""
+    rep = _REPS[rep]
+    nb = clover_bytes(dims, rep, F32)
+    out = []
+    for t in (c64.M, c64.Minv):
+        o = _empty(nb, t.device)
+        _check(_lib.hrd_convert_clover(ctypes.byref(lattice(dims)), rep, _ptr(t), _ptr(o), _stream()))
+        out.append(o)
+    return Clover(out[0], out[1], F32)
+
+
+def unpack_clover(C64, dims, rep):
+    """Packed FP64 clover field -> complex128 [V, 4N, 4N]."""
+    rep = _REPS[rep]
+    g = Geometry(tuple(dims), rep)
+    _need(C64, clover_bytes(dims, rep, F64), "C64")
+    n = 4 * g.ncolour
+    out = torch.empty((g.volume, n, n), dtype=torch.complex128, device=C64.device)
+    _check(_lib.hrd_unpack_clover(ctypes.byref(lattice(dims)), rep, _ptr(C64), _ptr(out), _stream()))
+    return out
+
+
+def dirac_apply_clover(U, clov, psi, rep, parity, dims, dagger=False, out=None, work=None):
+    """out = D_sw psi ('full') or D^_sw psi_e ('eo'); precision is that of clov."""
+    rep, parity, prec = _REPS[rep], _PARITIES[parity], clov.prec
+    np_ = 2 if parity == FULL else 1
+    nbytes = spinor_bytes(dims, rep, prec, np_)
+    _need(psi, nbytes, "psi")
+    _need(U, gauge_bytes(dims, rep, prec), "U")
+    if out is None:
+        out = _empty(nbytes, psi.device)
+    wb = dirac_workspace_bytes(dims, rep, prec, parity)
+    if wb and work is None:
+        work = _empty(wb, psi.device)
+    _check(_lib.hrd_dirac_apply_clover(ctypes.byref(lattice(dims)), rep, prec, _ptr(U), _ptr(clov.M),
+                                       _ptr(clov.Minv), _ptr(psi), _ptr(out), parity, int(bool(dagger)),
+                                       _ptr(work) if wb else None, _stream()))
+    return out
+
+
+class CloverOp:
+    """Prepared ``dirac_apply_clover`` (one foreign call per application)."""
+
+    def __init__(self, U, clov, dims, rep, parity, dagger=False):
+        self.rep, self.prec, self.parity = _REPS[rep], clov.prec, _PARITIES[parity]
+        _need(U, gauge_bytes(dims, self.rep, self.prec), "U")
+        self._keep = (U, clov)
+        self._lat = lattice(dims)
+        self._lat_ref = ctypes.byref(self._lat)
+        np_ = 2 if self.parity == FULL else 1
+        self.field_bytes = spinor_bytes(dims, self.rep, self.prec, np_)
+        wb = dirac_workspace_bytes(dims, self.rep, self.prec, self.parity)
+        self._work = _empty(wb, U.device) if wb else None
+        self._args = (U.data_ptr(), clov.M.data_ptr(), clov.Minv.data_ptr())
+        self._wptr = self._work.data_ptr() if wb else None
+        self._dag = int(bool(dagger))
+        self._stream = torch.cuda.current_stream().cuda_stream
+
+    def __call__(self, src, dst):
+        _need(src, self.field_bytes, "src")
+        _need(dst, self.field_bytes, "dst")
+        st = _lib.hrd_dirac_apply_clover(self._lat_ref, self.rep, self.prec, *self._args, src.data_ptr(),
+                                         dst.data_ptr(), self.parity, self._dag, self._wptr, self._stream)
+        if st != OK:
+            _check(st)
+        return dst
+
+
+def cg_solve_clover(U64, clov64, b, tol, dims, rep, mode="f64", U32=None, clov32=None, x0=None, maxiter=10000,
+                    delta=0.1, work=None, allow_noconv=False):
+    """Solve (D^_sw^+ D^_sw) x = b on even sites; returns (x, info dict)."""
+    rep, mode = _REPS[rep], _MODES[mode]
+    nb = spinor_bytes(dims, rep, F64, 1)
+    _need(b, nb, "b")
+    x = _zeros(nb, b.device) if x0 is None else x0.clone()
+    wb = cg_workspace_bytes(dims, rep, mode)
+    if work is None:
+        work = _empty(wb, b.device)
+    info = CgInfo()
+    M32 = clov32.M if clov32 is not None else None
+    Mi32 = clov32.Minv if clov32 is not None else None
+    st = _lib.hrd_cg_solve_clover(ctypes.byref(lattice(dims)), rep, mode, _ptr(U64), _ptr(U32), _ptr(clov64.M),
+                                  _ptr(clov64.Minv), _ptr(M32), _ptr(Mi32), _ptr(b), _ptr(x), float(tol),
+                                  int(maxiter), float(delta), _ptr(work), wb, ctypes.byref(info), _stream())
     _check(st, allow=(ENOCONV,) if allow_noconv else ())
     d = info.as_dict()
     d["status"] = _STATUS_NAMES[st]

@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_the_api():
     names = declared_functions()
     for must in ("hrd_dirac_apply", "hrd_cg_solve", "hrd_dirac_force", "hrd_dirac_apply_batched",
-                 "hrd_cg_solve_batched", "hrd_autotune_batched", "hrd_represent", "hrd_pack_gauge"):
+                 "hrd_cg_solve_batched", "hrd_autotune_batched", "hrd_represent", "hrd_pack_gauge",
+                 "hrd_clover_build", "hrd_dirac_apply_clover", "hrd_cg_solve_clover"):
         assert must in names
     assert len(names) >= 28
 
@@ -61,3 +62,25 @@ def test_host_side_queries(lib):
     lib.hrd_dirac_apply.restype = ctypes.c_int
     assert lib.hrd_dirac_apply(ctypes.byref(bad), 0, 0, None, None, None, ctypes.c_double(0.0), 0, 0, None, None) == 2
     assert lib.hrd_dirac_apply(ctypes.byref(good), 7, 0, None, None, None, ctypes.c_double(0.0), 0, 0, None, None) == 1
+
+
+def test_clover_queries(lib):
+    class Lat(ctypes.Structure):
+        _fields_ = [("dims", ctypes.c_int * 4)]
+
+    lib.hrd_clover_bytes.restype = ctypes.c_size_t
+    good = Lat((ctypes.c_int * 4)(8, 8, 8, 8))
+    V = 8 ** 4
+    # 8 N^2 reals per site: N = 2 (FUND, FUND_SU2), 3 (ADJ, ADJ_SU2)
+    assert lib.hrd_clover_bytes(ctypes.byref(good), 0, 0) == V * 32 * 8
+    assert lib.hrd_clover_bytes(ctypes.byref(good), 2, 1) == V * 32 * 4
+    assert lib.hrd_clover_bytes(ctypes.byref(good), 1, 0) == V * 72 * 8
+    assert lib.hrd_clover_bytes(ctypes.byref(good), 3, 1) == V * 72 * 4
+    assert lib.hrd_clover_bytes(ctypes.byref(good), 9, 0) == 0
+    # argument errors before any device work
+    lib.hrd_dirac_apply_clover.restype = ctypes.c_int
+    assert lib.hrd_dirac_apply_clover(ctypes.byref(good), 0, 0, None, None, None, None, None, 2, 0, None, None) == 1
+    assert lib.hrd_dirac_apply_clover(ctypes.byref(good), 0, 0, None, None, None, None, None, 0, 0, None, None) == 1
+    lib.hrd_clover_build.restype = ctypes.c_int
+    assert lib.hrd_clover_build(ctypes.byref(good), 0, None, ctypes.c_double(1.0), ctypes.c_double(0.0), None,
+                                None, None) == 1
