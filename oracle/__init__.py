@@ -315,39 +315,59 @@ def apply_site_matrix(M, psi):
     return np.einsum("...ij,...j->...i", M, flat).reshape(psi.shape)
 
 
-def dirac_clover(U, psi, m0, csw):
-    """D_sw psi = D psi + A psi."""
-    return dirac(U, psi, m0) + apply_site_matrix(clover(U, csw), psi)
+def expm_hermitian(X):
+    """exp(X) of Hermitian matrices [..., n, n] through the eigendecomposition
+    X = W diag(lam) W^+ (a library primitive)."""
+    lam, W = np.linalg.eigh(X)
+    return np.einsum("...ij,...j,...kj->...ik", W, np.exp(lam), np.conj(W))
 
 
-def dirac_clover_dagger(U, psi, m0, csw):
-    return apply_gamma5(dirac_clover(U, apply_gamma5(psi), m0, csw))
+def clover_diag(U, m0, csw, kind="sw"):
+    """Site-diagonal block M(x) of the improved operator and its inverse.
 
-
-def clover_diag(U, m0, csw):
-    """M(x) = (4 + m0) + A(x), the site-diagonal block of D_sw, and its inverse."""
+    kind "sw":  M = m + A (Sheikholeslami-Wohlert), inverse by LAPACK.
+    kind "exp": M = m exp(A / m) (exponentiated clover; Sec. 2.2 names it
+                without a formula, the reading is the one whose first order
+                in c_sw is the "sw" term), inverse (1/m) exp(-A / m).
+    m = 4 + m0."""
     A = clover(U, csw)
     n4 = A.shape[-1]
-    M = A + (4.0 + m0) * np.eye(n4)
-    return M, np.linalg.inv(M)
+    m = 4.0 + m0
+    if kind == "sw":
+        M = A + m * np.eye(n4)
+        return M, np.linalg.inv(M)
+    if kind == "exp":
+        return m * expm_hermitian(A / m), expm_hermitian(-A / m) / m
+    raise ValueError(f"unknown clover kind {kind!r}")
 
 
-def dhat_clover(U, psi_e, m0, csw, Mfields=None):
+def dirac_clover(U, psi, m0, csw, kind="sw"):
+    """D_sw psi = (M - H/2) psi: the Wilson D with its mass term m replaced by M(x)."""
+    M, _ = clover_diag(U, m0, csw, kind)
+    m = 4.0 + m0
+    return dirac(U, psi, m0) - m * psi + apply_site_matrix(M, psi)
+
+
+def dirac_clover_dagger(U, psi, m0, csw, kind="sw"):
+    return apply_gamma5(dirac_clover(U, apply_gamma5(psi), m0, csw, kind))
+
+
+def dhat_clover(U, psi_e, m0, csw, Mfields=None, kind="sw"):
     """D^ = M_ee - D_eo M_oo^{-1} D_oe on even sites (Schur complement of D_sw)."""
-    M, Minv = clover_diag(U, m0, csw) if Mfields is None else Mfields
+    M, Minv = clover_diag(U, m0, csw, kind) if Mfields is None else Mfields
     psi_e = restrict(psi_e, 0)
     t_o = apply_site_matrix(Minv, hop_block(U, psi_e, 1))
     t_o = restrict(t_o, 1)
     return restrict(apply_site_matrix(M, psi_e), 0) - hop_block(U, t_o, 0)
 
 
-def dhat_clover_dagger(U, psi_e, m0, csw, Mfields=None):
-    return apply_gamma5(dhat_clover(U, apply_gamma5(psi_e), m0, csw, Mfields))
+def dhat_clover_dagger(U, psi_e, m0, csw, Mfields=None, kind="sw"):
+    return apply_gamma5(dhat_clover(U, apply_gamma5(psi_e), m0, csw, Mfields, kind))
 
 
-def cg_clover(U, b_e, m0, csw, tol=1e-10, maxiter=10000):
+def cg_clover(U, b_e, m0, csw, tol=1e-10, maxiter=10000, kind="sw"):
     """CG on D^+ D^ for the clover operator."""
-    Mf = clover_diag(U, m0, csw)
+    Mf = clover_diag(U, m0, csw, kind)
 
     def op(v):
         return dhat_clover_dagger(U, dhat_clover(U, v, m0, csw, Mf), m0, csw, Mf)
@@ -355,8 +375,8 @@ def cg_clover(U, b_e, m0, csw, tol=1e-10, maxiter=10000):
     return cg(U, b_e, m0, tol=tol, maxiter=maxiter, op=op)
 
 
-def true_residual_clover(U, b_e, x_e, m0, csw):
-    Mf = clover_diag(U, m0, csw)
+def true_residual_clover(U, b_e, x_e, m0, csw, kind="sw"):
+    Mf = clover_diag(U, m0, csw, kind)
     b_e = restrict(_cplx(b_e), 0)
     Ax = dhat_clover_dagger(U, dhat_clover(U, restrict(_cplx(x_e), 0), m0, csw, Mf), m0, csw, Mf)
     return norm(b_e - Ax) / norm(b_e)

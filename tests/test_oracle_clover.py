@@ -10,7 +10,11 @@ paper gives no formula, the reading is stated in oracle/oracle.c).
   — pins the leaf orientation, the 1/8 and the i/4;
 * gauge covariance A[U^g](x) = g(x) A[U](x) g(x)^+ and of D_sw;
 * an independent dense D_sw: the Schur complement equals the even/odd
-  operator M_ee - D_eo M_oo^-1 D_oe, determinants factorise, CG solves it.
+  operator M_ee - D_eo M_oo^-1 D_oe, determinants factorise, CG solves it;
+* the exponentiated clover M = m exp(A/m): the matrix exponential agrees
+  with scipy's Pade-based expm and with its power series, M vanishes to
+  m at c_sw = 0, equals m exp(diag/m) for the abelian field, agrees with
+  m + A + A^2/(2m) to third order in c_sw, and M^{-1} = exp(-A/m)/m.
 """
 import numpy as np
 import pytest
@@ -92,17 +96,20 @@ def test_clover_gauge_covariance(oracle, n):
     assert np.abs(lhs - rhs).max() < 1e-12
 
 
+@pytest.mark.parametrize("kind", ["sw", "exp"])
 @pytest.mark.parametrize("dims,n", [((2, 2, 2, 2), 2), ((4, 2, 2, 2), 2), ((2, 2, 2, 2), 3)])
-def test_clover_dense_schur(oracle, dims, n):
+def test_clover_dense_schur(oracle, dims, n, kind):
     m0, csw = -0.3, 1.2
+    m = 4.0 + m0
     U = _links(dims, n, 11, oracle)
     D = dense.dirac_matrix(U, m0)
-    A = oracle.clover(U, csw).reshape(-1, 4 * n, 4 * n)
+    M, _ = oracle.clover_diag(U, m0, csw, kind)
+    A = M.reshape(-1, 4 * n, 4 * n) - m * np.eye(4 * n)
     blk = 4 * n
     for s in range(A.shape[0]):
         D[s * blk:(s + 1) * blk, s * blk:(s + 1) * blk] += A[s]
     psi = inputs.gaussian_spinor(dims, n, 12)
-    assert np.abs(oracle.dirac_clover(U, psi, m0, csw).ravel() - D @ psi.ravel()).max() < 1e-13
+    assert np.abs(oracle.dirac_clover(U, psi, m0, csw, kind).ravel() - D @ psi.ravel()).max() < 1e-13
     Dee, Deo, Doe, Doo = dense.schur_blocks(D, dims, n)
     S = Dee - Deo @ np.linalg.solve(Doo, Doe)
     e, _ = dense.parity_index(dims, n)
@@ -111,7 +118,7 @@ def test_clover_dense_schur(oracle, dims, n):
     for k in range(len(e)):
         v = np.zeros(int(np.prod(shape)), np.complex128)
         v[e[k]] = 1
-        cols[:, k] = oracle.dhat_clover(U, v.reshape(shape), m0, csw).ravel()[e]
+        cols[:, k] = oracle.dhat_clover(U, v.reshape(shape), m0, csw, kind=kind).ravel()[e]
     assert np.abs(cols - S).max() < 1e-13
     _, ld = np.linalg.slogdet(D)
     _, lh = np.linalg.slogdet(S)
@@ -120,15 +127,81 @@ def test_clover_dense_schur(oracle, dims, n):
     # g5-hermiticity of the clover D^
     phe = oracle.restrict(inputs.gaussian_spinor(dims, n, 13), 0)
     pse = oracle.restrict(psi, 0)
-    lhs = oracle.inner(phe, oracle.dhat_clover(U, pse, m0, csw))
-    rhs = oracle.inner(oracle.dhat_clover_dagger(U, phe, m0, csw), pse)
+    lhs = oracle.inner(phe, oracle.dhat_clover(U, pse, m0, csw, kind=kind))
+    rhs = oracle.inner(oracle.dhat_clover_dagger(U, phe, m0, csw, kind=kind), pse)
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
-def test_clover_cg(oracle):
+@pytest.mark.parametrize("kind", ["sw", "exp"])
+def test_clover_cg(oracle, kind):
     dims, n, m0, csw = (4, 4, 2, 4), 2, -0.2, 1.0
     U = _links(dims, n, 21, oracle, kind="smeared")
     b = oracle.restrict(inputs.gaussian_spinor(dims, n, 22), 0)
-    x, info = oracle.cg_clover(U, b, m0, csw, tol=1e-11)
+    x, info = oracle.cg_clover(U, b, m0, csw, tol=1e-11, kind=kind)
     assert info["true_rel_residual"] <= 1e-11
-    assert oracle.true_residual_clover(U, b, x, m0, csw) <= 1e-11
+    assert oracle.true_residual_clover(U, b, x, m0, csw, kind=kind) <= 1e-11
+
+
+def test_expm_hermitian_pins(oracle):
+    import scipy.linalg
+
+    rng = np.random.default_rng(5)
+    for n in (4, 6):
+        Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        X = (Z + Z.conj().T) / 4
+        E = oracle.expm_hermitian(X)
+        assert np.abs(E - scipy.linalg.expm(X)).max() < 1e-13 * np.abs(E).max()
+        # power series, summed until the terms vanish
+        S, T = np.eye(n, dtype=complex), np.eye(n, dtype=complex)
+        for k in range(1, 60):
+            T = T @ X / k
+            S = S + T
+        assert np.abs(E - S).max() < 1e-13 * np.abs(E).max()
+        assert np.abs(E @ oracle.expm_hermitian(-X) - np.eye(n)).max() < 1e-13
+    d = np.array([0.3, -1.2, 2.0])
+    assert np.abs(oracle.expm_hermitian(np.diag(d)) - np.diag(np.exp(d))).max() < 1e-15 * np.exp(2.0)
+
+
+def test_exp_clover_special_cases(oracle):
+    m0 = -0.3
+    m = 4.0 + m0
+    # c_sw = 0: M = m, M^{-1} = 1/m
+    U = _links((4, 2, 2, 2), 2, 3, oracle)
+    M, Mi = oracle.clover_diag(U, m0, 0.0, "exp")
+    assert np.abs(M - m * np.eye(8)).max() < 1e-14 and np.abs(Mi - np.eye(8) / m).max() < 1e-15
+    # abelian constant field: A is diagonal, so M = m exp(diag(A)/m) elementwise
+    dims, k, csw = (2, 4, 6, 2), 1, 1.9
+    phi = 2 * np.pi * k / dims[2]
+    U = np.zeros((4,) + dims + (2, 2), np.complex128)
+    U[..., 0, 0] = 1
+    U[..., 1, 1] = 1
+    x2 = np.arange(dims[2]).reshape(1, 1, -1, 1)
+    U[1, ..., 0, 0] = np.exp(1j * phi * x2)
+    U[1, ..., 1, 1] = np.exp(-1j * phi * x2)
+    a = -(csw / 2) * np.sin(phi) * np.kron([1, -1, 1, -1], [1, -1])
+    M, Mi = oracle.clover_diag(U, m0, csw, "exp")
+    assert np.abs(M - np.diag(m * np.exp(a / m))).max() < 1e-14
+    assert np.abs(Mi - np.diag(np.exp(-a / m) / m)).max() < 1e-15
+    # small c_sw: m exp(A/m) = m + A + A^2/(2m) + O(c_sw^3)
+    U = _links((4, 2, 2, 2), 3, 9, oracle)
+    errs = []
+    for c in (0.02, 0.04):
+        A = oracle.clover(U, c)
+        M, Mi = oracle.clover_diag(U, m0, c, "exp")
+        errs.append(np.abs(M - m * np.eye(12) - A - A @ A / (2 * m)).max())
+        assert np.abs(M @ Mi - np.eye(12)).max() < 1e-14
+    assert 6.0 < errs[1] / errs[0] < 10.0  # third order
+
+
+def test_exp_clover_covariance(oracle):
+    dims = (4, 2, 4, 2)
+    rng = inputs.rng_for(7)
+    Uf = inputs.gauge_field(dims, 8)
+    g = inputs.gauge_transform(rng, dims)
+    Ug = np.empty_like(Uf)
+    for mu in range(4):
+        Ug[mu] = g @ Uf[mu] @ np.conj(np.swapaxes(np.roll(g, -1, axis=mu), -1, -2))
+    G = np.einsum("ab,...ij->...aibj", np.eye(4), g).reshape(g.shape[:-2] + (8, 8))
+    M, _ = oracle.clover_diag(Uf, -0.2, 1.3, "exp")
+    Mt, _ = oracle.clover_diag(Ug, -0.2, 1.3, "exp")
+    assert np.abs(Mt - G @ M @ np.conj(np.swapaxes(G, -1, -2))).max() < 1e-13
