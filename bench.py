@@ -13,7 +13,10 @@ One step = one pass over every stage of the hot path:
   3. CG on D^+D^ to true residual 1e-10 in FP64 and in mixed precision;
   4. the fermion-action force from the mixed solution;
   5. a batched 12-right-hand-side FP32 D^ in persistent launches (when the
-     library provides it).
+     library provides it);
+  6. the clover-improved operator (Sec. 2.2), Sheikholeslami-Wohlert and
+     exponentiated, c_sw = 1: site-matrix build, even/odd D^_sw in FP64 and
+     FP32, and CG on D^_sw^+ D^_sw in FP64 and mixed precision.
 
 Prints one JSON line.  `value` is the FP64 Dslash (hopping block) bandwidth
 on algorithmic bytes: each link, each source spinor and each output spinor
@@ -56,6 +59,17 @@ def dhat_alg_bytes(V, rep, prec):
     """D^ = two hops plus the m*psi read of the second: V (8L + 2.5 S)."""
     L, S = LINK_BYTES[(rep, prec)], SPINOR_BYTES[(rep, prec)]
     return V * (8 * L) + (V // 2) * 5 * S
+
+
+def clover_site_bytes(rep, prec):
+    """Packed clover field: 8 N^2 reals per site."""
+    n = 2 if rep in ("fund", "fund_su2") else 3
+    return 8 * n * n * (8 if prec == "f64" else 4)
+
+
+def dhat_clover_alg_bytes(V, rep, prec):
+    """D^_sw: the D^ bytes plus M^{-1} on odd and M on even sites, each read once."""
+    return dhat_alg_bytes(V, rep, prec) + V * clover_site_bytes(rep, prec)
 
 
 KERNEL_SOURCES = ["paper_2411_18511_amd/csrc/dslash.hip", "paper_2411_18511_amd/csrc/common.h",
@@ -216,6 +230,8 @@ def main():
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     LINK_FORMATS = ("fund", "fund_su2")
+    CLOVER_KINDS = ("sw", "exp")
+    CSW = 1.0
 
     def timed(fn, reps):
         a, b = ev(), ev()
@@ -285,6 +301,23 @@ def main():
                 r[f"batched_dhat_{fmt}"] = timed(lambda: hrd.dirac_apply_batched(probs, "eo", tune=tunes[fmt],
                                                                                  work=wb), 5)
                 del srcs, dsts, wb
+            # 6. clover-improved operator (fundamental links only)
+            if fmt == "fund":
+                for kind in CLOVER_KINDS:
+                    r[f"clover_build_{kind}_ms"], c64 = timed_once(
+                        lambda: hrd.clover_build(U64, CSW, m0, dims, fmt, kind=kind))
+                    c32 = hrd.convert_clover(c64, dims, fmt)
+                    cd64 = hrd.CloverOp(U64, c64, dims, fmt, "eo")
+                    cd32 = hrd.CloverOp(U32, c32, dims, fmt, "eo")
+                    r[f"dhat_clover_{kind}_f64"] = timed(lambda: cd64(src_e, out_e), R // 2)
+                    r[f"dhat_clover_{kind}_f32"] = timed(lambda: cd32(src_e32, out_e32), R // 2)
+                    r[f"cg_clover_{kind}_f64_ms"], (_, ic64) = timed_once(
+                        lambda: hrd.cg_solve_clover(U64, c64, src_e, tol, dims, fmt, mode="f64"))
+                    r[f"cg_clover_{kind}_mixed_ms"], (_, icm) = timed_once(
+                        lambda: hrd.cg_solve_clover(U64, c64, src_e, tol, dims, fmt, mode="mixed", U32=U32,
+                                                    clov32=c32))
+                    r[f"cg_clover_{kind}_f64"], r[f"cg_clover_{kind}_mixed"] = ic64, icm
+                    del c64, c32, cd64, cd32
             del U64, U32, x64, xm, d
         return r
 
@@ -338,6 +371,19 @@ def main():
             "mixed_vs_f64_solution_rel_diff": per[-1][f"mixed_vs_f64_rel_{fmt}"],
             "action_force_ms": avg(f"action_force_{fmt}_ms"),
         }
+    clover = {"csw": CSW, "rep": "fund"}
+    for kind in CLOVER_KINDS:
+        d_ = {"build_ms": avg(f"clover_build_{kind}_ms")}
+        for prec in ("f64", "f32"):
+            ms = avg(f"dhat_clover_{kind}_{prec}")
+            gbs = dhat_clover_alg_bytes(V, "fund", prec) / (ms * 1e-3) / 1e9
+            d_[f"dhat_{prec}"] = {"ms": ms, "alg_GBs": gbs, "pct_hbm_peak": 100.0 * gbs / HBM_PEAK_GBS,
+                                  "alg_bytes": dhat_clover_alg_bytes(V, "fund", prec),
+                                  "over_wilson_dhat": ms / avg(f"dhat_{prec}_fund")}
+        d_["cg_f64"] = {"ms": avg(f"cg_clover_{kind}_f64_ms"), **per[-1][f"cg_clover_{kind}_f64"]}
+        d_["cg_mixed"] = {"ms": avg(f"cg_clover_{kind}_mixed_ms"), **per[-1][f"cg_clover_{kind}_mixed"]}
+        d_["mixed_over_f64_time"] = d_["cg_mixed"]["ms"] / d_["cg_f64"]["ms"]
+        clover[kind] = d_
     hop = dslash["hop_f64_fund"]
     hop_gbs = hop["alg_GBs"]
     out = {
@@ -363,6 +409,7 @@ def main():
                      "alg_bytes_per_launch": hop_alg_bytes(V, "fund", "f64"), "avg_launch_ms": hop["ms"]},
         "dslash": dslash,
         "cg": cg,
+        "clover": clover,
         "copy_ceiling": ceiling,
     }
     tr = measured_traffic()

@@ -304,13 +304,23 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
 /* Bytes of one packed clover field (M or M^{-1}) of the given precision. */
 size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec);
 
-/* Builds M = (4 + m0) + A and M^{-1} (each block inverted by Gauss-Jordan
-   elimination with partial pivoting) in FP64 from the packed FP64 gauge
+/* Which site matrix hrd_clover_build forms (m = 4 + m0):
+     HRD_CLOVER_SW  : M = m + A (Sheikholeslami-Wohlert), M^{-1} by
+                      Gauss-Jordan elimination with partial pivoting;
+     HRD_CLOVER_EXP : M = m exp(A/m) (exponentiated clover, also named in
+                      Sec. 2.2), M^{-1} = (1/m) exp(-A/m); each exponential by
+                      scaling and squaring of a degree-16 Taylor polynomial.
+   Both agree to first order in c_sw; every operator and solver below takes
+   either. */
+typedef enum { HRD_CLOVER_SW = 0, HRD_CLOVER_EXP = 1 } hrd_clover_kind;
+
+/* Builds M and M^{-1} of the given kind in FP64 from the packed FP64 gauge
    field U64 of rep.  M64 and Minv64 receive hrd_clover_bytes(F64) bytes each.
-   A block that is singular yields non-finite entries (no error is raised:
-   M is not inspected on the host).  Asynchronous. */
-hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, const void *U64,
-                            double csw, double m0, void *M64, void *Minv64, void *stream);
+   For HRD_CLOVER_SW a singular block yields non-finite entries (no error is
+   raised: M is not inspected on the host).  Asynchronous. */
+hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind kind,
+                            const void *U64, double csw, double m0, void *M64,
+                            void *Minv64, void *stream);
 
 /* FP64 -> FP32 copy of a packed clover field (for the mixed-precision CG
    and FP32 operators).  Asynchronous. */

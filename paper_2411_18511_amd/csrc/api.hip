@@ -397,11 +397,12 @@ size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
     return clover_bytes(lat, rep, prec);
 }
 
-hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, const void *U64, double csw, double m0, void *M64,
-                            void *Minv64, void *stream)
+hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind kind, const void *U64, double csw,
+                            double m0, void *M64, void *Minv64, void *stream)
 {
     HRD_TRY(check_lattice(lat));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
+    if (kind != HRD_CLOVER_SW && kind != HRD_CLOVER_EXP) return fail(HRD_EINVAL, "invalid clover kind %d", (int)kind);
     if (!U64 || !M64 || !Minv64) return fail(HRD_EINVAL, "NULL field pointer");
     if (!std::isfinite(csw) || !std::isfinite(m0)) return fail(HRD_EINVAL, "csw and m0 must be finite");
     const size_t cb = clover_bytes(lat, rep, HRD_F64);
@@ -409,7 +410,9 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, const void *U64
     if (overlap(M64, cb, Minv64, cb) || overlap(M64, cb, U64, ub) || overlap(Minv64, cb, U64, ub))
         return fail(HRD_EALIAS, "clover outputs overlap each other or the gauge field");
     const Geom g = make_geom(lat->dims);
-    return check_hip(launch_clover_build(rep, g, U64, csw, 4.0 + m0, M64, Minv64, (hipStream_t)stream),
+    if (4.0 + m0 == 0.0) return fail(HRD_EINVAL, "m0 = -4 makes the mass term zero");
+    return check_hip(launch_clover_build(rep, kind == HRD_CLOVER_EXP, g, U64, csw, 4.0 + m0, M64, Minv64,
+                                         (hipStream_t)stream),
                      "clover_build launch");
 }
 

@@ -11,6 +11,12 @@
 //   A_dn = +sum_l s_l (x) Y_l,  Y_l = c_sw (i/2)(B_l - E_l).
 // The paper stores an LDL factorisation; here the inverse blocks themselves
 // are stored, so applying M^{-1} costs the same as applying M.
+//
+// The exponentiated variant (also named in Sec. 2.2) replaces m + A by
+// M = m exp(A/m), whose inverse (1/m) exp(-A/m) is again an exponential; each
+// Hermitian block is exponentiated by scaling and squaring around a Taylor
+// polynomial (X / 2^s with ||X / 2^s||_1 <= 1/4, degree 16: truncation below
+// 1e-24 relative before squaring).
 #include "clover.h"
 #include "kernels.h"
 
@@ -188,6 +194,54 @@ __device__ void invert(Cx<double> (&a)[M][M])
         for (int j = 0; j < M; j++) a[i][j] = inv[i][j];
 }
 
+// E = exp(c X) for a 2N x 2N block X (c = +-1/m), scaling and squaring.
+template <int M>
+__device__ void expm_block(const Cx<double> (&X)[M][M], double c, Cx<double> (&E)[M][M])
+{
+    double nrm = 0.0;
+    for (int j = 0; j < M; j++) {
+        double col = 0.0;
+        for (int i = 0; i < M; i++) col += fabs(X[i][j].re) + fabs(X[i][j].im);
+        nrm = fmax(nrm, col);
+    }
+    nrm *= fabs(c);
+    int sq = 0;
+    while (nrm > 0.25 && sq < 64) {
+        nrm *= 0.5;
+        sq++;
+    }
+    const double scale = ldexp(c, -sq);
+    Cx<double> Y[M][M], T[M][M];
+    for (int i = 0; i < M; i++)
+        for (int j = 0; j < M; j++) {
+            Y[i][j] = scale * X[i][j];
+            E[i][j] = Cx<double>{i == j ? 1.0 : 0.0, 0.0};
+        }
+    // Horner: E = I + Y/1 (I + Y/2 (... (I + Y/16)))
+    constexpr int kDegree = 16;
+    for (int k = kDegree; k >= 1; k--) {
+        const double rk = 1.0 / k;
+        for (int i = 0; i < M; i++)
+            for (int j = 0; j < M; j++) {
+                Cx<double> z = cmul(Y[i][0], E[0][j]);
+                for (int l = 1; l < M; l++) z = cfma(Y[i][l], E[l][j], z);
+                T[i][j] = rk * z;
+            }
+        for (int i = 0; i < M; i++)
+            for (int j = 0; j < M; j++) E[i][j] = Cx<double>{(i == j ? 1.0 : 0.0) + T[i][j].re, T[i][j].im};
+    }
+    for (int q = 0; q < sq; q++) {
+        for (int i = 0; i < M; i++)
+            for (int j = 0; j < M; j++) {
+                Cx<double> z = cmul(E[i][0], E[0][j]);
+                for (int l = 1; l < M; l++) z = cfma(E[i][l], E[l][j], z);
+                T[i][j] = z;
+            }
+        for (int i = 0; i < M; i++)
+            for (int j = 0; j < M; j++) E[i][j] = T[i][j];
+    }
+}
+
 template <int N>
 __device__ __forceinline__ void pack_block(const Cx<double> (&a)[2 * N][2 * N], double (&d)[2 * N],
                                            Cx<double> (&l)[N * (2 * N - 1)])
@@ -200,7 +254,7 @@ __device__ __forceinline__ void pack_block(const Cx<double> (&a)[2 * N][2 * N], 
     }
 }
 
-template <int REP>
+template <int REP, bool EXP>
 __global__ __launch_bounds__(64) void clover_build_kernel(Geom g, const void *U, double csw, double m, void *Mf,
                                                           void *Mi)
 {
@@ -243,20 +297,43 @@ __global__ __launch_bounds__(64) void clover_build_kernel(Geom g, const void *U,
             dn[N + i][j] = Y[0] + iY2;
             dn[N + i][N + j] = -Y[2];
         }
-#pragma unroll
-    for (int i = 0; i < B2; i++) {
-        up[i][i].re += m;
-        dn[i][i].re += m;
-    }
     CloverSite<N, double> c;
-    pack_block<N>(up, c.d[0], c.l[0]);
-    pack_block<N>(dn, c.d[1], c.l[1]);
-    clover_store<N, double>(Mf, g.Vh, p, idx, c);
-    invert<B2>(up);
-    invert<B2>(dn);
-    pack_block<N>(up, c.d[0], c.l[0]);
-    pack_block<N>(dn, c.d[1], c.l[1]);
-    clover_store<N, double>(Mi, g.Vh, p, idx, c);
+    if constexpr (EXP) {
+        Cx<double> E[B2][B2];
+        expm_block<B2>(up, 1.0 / m, E);
+        for (int i = 0; i < B2; i++)
+            for (int j = 0; j < B2; j++) E[i][j] = m * E[i][j];
+        pack_block<N>(E, c.d[0], c.l[0]);
+        expm_block<B2>(dn, 1.0 / m, E);
+        for (int i = 0; i < B2; i++)
+            for (int j = 0; j < B2; j++) E[i][j] = m * E[i][j];
+        pack_block<N>(E, c.d[1], c.l[1]);
+        clover_store<N, double>(Mf, g.Vh, p, idx, c);
+        const double rm = 1.0 / m;
+        expm_block<B2>(up, -rm, E);
+        for (int i = 0; i < B2; i++)
+            for (int j = 0; j < B2; j++) E[i][j] = rm * E[i][j];
+        pack_block<N>(E, c.d[0], c.l[0]);
+        expm_block<B2>(dn, -rm, E);
+        for (int i = 0; i < B2; i++)
+            for (int j = 0; j < B2; j++) E[i][j] = rm * E[i][j];
+        pack_block<N>(E, c.d[1], c.l[1]);
+        clover_store<N, double>(Mi, g.Vh, p, idx, c);
+    } else {
+#pragma unroll
+        for (int i = 0; i < B2; i++) {
+            up[i][i].re += m;
+            dn[i][i].re += m;
+        }
+        pack_block<N>(up, c.d[0], c.l[0]);
+        pack_block<N>(dn, c.d[1], c.l[1]);
+        clover_store<N, double>(Mf, g.Vh, p, idx, c);
+        invert<B2>(up);
+        invert<B2>(dn);
+        pack_block<N>(up, c.d[0], c.l[0]);
+        pack_block<N>(dn, c.d[1], c.l[1]);
+        clover_store<N, double>(Mi, g.Vh, p, idx, c);
+    }
 }
 
 // F64 -> F32 packed clover field: real r of a site lives in F64 plane r/2 and
@@ -304,19 +381,33 @@ __global__ __launch_bounds__(kBlock) void unpack_clover_kernel(Geom g, const voi
 
 }  // namespace
 
-hipError_t launch_clover_build(int rep, const Geom &g, const void *U, double csw, double m, void *Mf, void *Mi,
-                               hipStream_t st)
+template <bool EXP>
+hipError_t launch_build(int rep, const Geom &g, const void *U, double csw, double m, void *Mf, void *Mi,
+                        hipStream_t st)
 {
     const dim3 grid((unsigned)((2L * g.Vh + 63) / 64)), block(64);
     switch (rep) {
-        case HRD_FUND: hipLaunchKernelGGL(clover_build_kernel<HRD_FUND>, grid, block, 0, st, g, U, csw, m, Mf, Mi); break;
-        case HRD_ADJ: hipLaunchKernelGGL(clover_build_kernel<HRD_ADJ>, grid, block, 0, st, g, U, csw, m, Mf, Mi); break;
-        case HRD_FUND_SU2:
-            hipLaunchKernelGGL(clover_build_kernel<HRD_FUND_SU2>, grid, block, 0, st, g, U, csw, m, Mf, Mi);
+        case HRD_FUND:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_FUND, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
             break;
-        default: hipLaunchKernelGGL(clover_build_kernel<HRD_ADJ_SU2>, grid, block, 0, st, g, U, csw, m, Mf, Mi); break;
+        case HRD_ADJ:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_ADJ, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
+            break;
+        case HRD_FUND_SU2:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_FUND_SU2, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
+            break;
+        default:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_ADJ_SU2, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
+            break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_clover_build(int rep, bool exponential, const Geom &g, const void *U, double csw, double m, void *Mf,
+                               void *Mi, hipStream_t st)
+{
+    return exponential ? launch_build<true>(rep, g, U, csw, m, Mf, Mi, st)
+                       : launch_build<false>(rep, g, U, csw, m, Mf, Mi, st);
 }
 
 hipError_t launch_convert_clover(int rep, const Geom &g, const void *C64, void *C32, hipStream_t st)

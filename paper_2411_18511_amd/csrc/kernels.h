@@ -105,9 +105,10 @@ hipError_t launch_copy(size_t bytes, const void *src, void *dst, hipStream_t st)
 hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st);
 
 // ----- clover term (clover.hip) ---------------------------------------------
-// M = m + A and M^{-1} of every site from the F64 links of the representation.
-hipError_t launch_clover_build(int rep, const Geom &g, const void *U, double csw, double m, void *M, void *Minv,
-                               hipStream_t st);
+// M = m + A (or m exp(A/m)) and M^{-1} of every site from the F64 links of
+// the representation.
+hipError_t launch_clover_build(int rep, bool exponential, const Geom &g, const void *U, double csw, double m, void *M,
+                               void *Minv, hipStream_t st);
 hipError_t launch_convert_clover(int rep, const Geom &g, const void *C64, void *C32, hipStream_t st);
 // packed F64 -> complex128 [V][4N][4N], lexicographic sites
 hipError_t launch_unpack_clover(int rep, const Geom &g, const void *C, void *nat, hipStream_t st);

@@ -115,7 +115,7 @@ _sig("hrd_blas_xpay", _I, _LP, _I, _I, _I, _P, _D, _D, _P, _P)
 _sig("hrd_cg_workspace_bytes", _S, _LP, _I, _I)
 _sig("hrd_cg_solve", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _D, _I, _D, _P, _S, ctypes.POINTER(CgInfo), _P)
 _sig("hrd_clover_bytes", _S, _LP, _I, _I)
-_sig("hrd_clover_build", _I, _LP, _I, _P, _D, _D, _P, _P, _P)
+_sig("hrd_clover_build", _I, _LP, _I, _I, _P, _D, _D, _P, _P, _P)
 _sig("hrd_convert_clover", _I, _LP, _I, _P, _P, _P)
 _sig("hrd_unpack_clover", _I, _LP, _I, _P, _P, _P)
 _sig("hrd_dirac_apply_clover", _I, _LP, _I, _I, _P, _P, _P, _P, _P, _I, _I, _P, _P)
@@ -428,14 +428,19 @@ class Clover:
     prec: int
 
 
-def clover_build(U64, csw, m0, dims, rep):
-    """FP64 M = (4 + m0) + A and M^{-1} from the packed FP64 gauge field."""
+CLOVER_SW, CLOVER_EXP = 0, 1
+_CLOVER_KINDS = {"sw": CLOVER_SW, "exp": CLOVER_EXP, CLOVER_SW: CLOVER_SW, CLOVER_EXP: CLOVER_EXP}
+
+
+def clover_build(U64, csw, m0, dims, rep, kind="sw"):
+    """FP64 M and M^{-1} from the packed FP64 gauge field: kind 'sw' builds
+    M = (4 + m0) + A, kind 'exp' builds M = m exp(A/m)."""
     rep = _REPS[rep]
     nb = clover_bytes(dims, rep, F64)
     _need(U64, gauge_bytes(dims, rep, F64), "U64")
     M, Minv = _empty(nb, U64.device), _empty(nb, U64.device)
-    _check(_lib.hrd_clover_build(ctypes.byref(lattice(dims)), rep, _ptr(U64), float(csw), float(m0), _ptr(M),
-                                 _ptr(Minv), _stream()))
+    _check(_lib.hrd_clover_build(ctypes.byref(lattice(dims)), rep, _CLOVER_KINDS[kind], _ptr(U64), float(csw),
+                                 float(m0), _ptr(M), _ptr(Minv), _stream()))
     return Clover(M, Minv, F64)
 
 

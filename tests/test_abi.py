@@ -82,5 +82,7 @@ def test_clover_queries(lib):
     assert lib.hrd_dirac_apply_clover(ctypes.byref(good), 0, 0, None, None, None, None, None, 2, 0, None, None) == 1
     assert lib.hrd_dirac_apply_clover(ctypes.byref(good), 0, 0, None, None, None, None, None, 0, 0, None, None) == 1
     lib.hrd_clover_build.restype = ctypes.c_int
-    assert lib.hrd_clover_build(ctypes.byref(good), 0, None, ctypes.c_double(1.0), ctypes.c_double(0.0), None,
+    assert lib.hrd_clover_build(ctypes.byref(good), 0, 0, None, ctypes.c_double(1.0), ctypes.c_double(0.0), None,
+                                None, None) == 1
+    assert lib.hrd_clover_build(ctypes.byref(good), 0, 5, None, ctypes.c_double(1.0), ctypes.c_double(0.0), None,
                                 None, None) == 1

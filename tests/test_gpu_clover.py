@@ -1,8 +1,9 @@
 """GPU parity of the clover-improved operator (Sec. 2.2: the extra site-diagonal
 term whose fields are precomputed once per gauge field).
 
-* the built site matrices M = m + A and M^{-1} equal the oracle's (which
-  inverts with LAPACK) to FP64 rounding;
+* the built site matrices M = m + A (or m exp(A/m)) and M^{-1} equal the
+  oracle's (which inverts with LAPACK and exponentiates through eigh) to
+  FP64 rounding;
 * D_sw (full lattice) and the even/odd D^_sw, with and without dagger, in
   FP64 and FP32, for every link format, equal the oracle to 1e-13 / 1e-6;
 * c_sw = 0 reduces to the Wilson operator;
@@ -33,23 +34,23 @@ def oracle():
 _cache = {}
 
 
-def setup(dims, rep, oracle, m0=-0.3, csw=1.4, seed=31, kind="smeared"):
-    key = (dims, rep, m0, csw, seed, kind)
+def setup(dims, rep, oracle, m0=-0.3, csw=1.4, seed=31, gauge="smeared", kind="sw"):
+    key = (dims, rep, m0, csw, seed, gauge, kind)
     if key not in _cache:
         h = hrd()
-        F = Field(dims, rep, seed=seed, kind=kind)
-        c64 = h.clover_build(F.U64, csw, m0, dims, rep)
+        F = Field(dims, rep, seed=seed, kind=gauge)
+        c64 = h.clover_build(F.U64, csw, m0, dims, rep, kind=kind)
         c32 = h.convert_clover(c64, dims, rep)
-        Mf = oracle.clover_diag(F.U_orc, m0, csw)
+        Mf = oracle.clover_diag(F.U_orc, m0, csw, kind)
         _cache.clear()
         _cache[key] = (F, c64, c32, Mf)
     return _cache[key]
 
 
-@pytest.mark.parametrize("rep,dims", [(r, d) for r in REPS for d in LATS[:2]])
-def test_clover_fields(oracle, rep, dims):
+@pytest.mark.parametrize("rep,dims,kind", [(r, d, k) for r in REPS for d in LATS[:2] for k in ("sw", "exp")])
+def test_clover_fields(oracle, rep, dims, kind):
     h = hrd()
-    F, c64, _, (M, Minv) = setup(dims, rep, oracle)
+    F, c64, _, (M, Minv) = setup(dims, rep, oracle, kind=kind)
     V = int(np.prod(dims))
     n4 = 4 * F.n
     gM = h.unpack_clover(c64.M, dims, rep).cpu().numpy().reshape(M.shape)
@@ -63,16 +64,16 @@ def test_clover_fields(oracle, rep, dims):
     assert np.all(gM[..., : 2 * F.n, 2 * F.n:] == 0)
 
 
-@pytest.mark.parametrize("rep,dims", [(r, d) for r in REPS for d in LATS])
-def test_clover_operator(oracle, rep, dims):
+@pytest.mark.parametrize("rep,dims,kind", [(r, d, k) for r in REPS for d in LATS for k in ("sw", "exp")])
+def test_clover_operator(oracle, rep, dims, kind):
     """D_sw and D^_sw, both daggers, FP64 and FP32."""
     h = hrd()
     m0, csw = -0.3, 1.4
-    F, c64, c32, Mf = setup(dims, rep, oracle)
+    F, c64, c32, Mf = setup(dims, rep, oracle, kind=kind)
     psi = F.spinor(41)
     e = oracle.restrict(F.spinor(43), 0)
     for dagger in (False, True):
-        want_full = (oracle.dirac_clover_dagger if dagger else oracle.dirac_clover)(F.U_orc, psi, m0, csw)
+        want_full = (oracle.dirac_clover_dagger if dagger else oracle.dirac_clover)(F.U_orc, psi, m0, csw, kind)
         want_eo = (oracle.dhat_clover_dagger if dagger else oracle.dhat_clover)(F.U_orc, e, m0, csw, Mf)
         for prec in ("f64", "f32"):
             U = F.U64 if prec == "f64" else F.U32
@@ -102,20 +103,21 @@ def test_csw_zero_is_wilson(oracle, rep):
     assert rel_err(a, b) < 1e-15
 
 
-@pytest.mark.parametrize("rep,mode", [(r, m) for r in ("fund", "adj", "fund_su2") for m in ("f64", "mixed")])
-def test_clover_cg(oracle, rep, mode):
+@pytest.mark.parametrize("rep,mode,kind", [(r, m, k) for r in ("fund", "adj", "fund_su2") for k in ("sw", "exp")
+                                           for m in ("f64", "mixed")])
+def test_clover_cg(oracle, rep, mode, kind):
     h = hrd()
     dims, m0, csw = (6, 4, 6, 10), -0.3, 1.4
-    F, c64, c32, Mf = setup(dims, rep, oracle)
+    F, c64, c32, Mf = setup(dims, rep, oracle, kind=kind)
     b_np = oracle.restrict(F.spinor(61), 0)
     b = F.pack(b_np, "f64", "even")
     x, info = h.cg_solve_clover(F.U64, c64, b, 1e-10, dims, rep, mode=mode, U32=F.U32, clov32=c32)
     assert info["status"] == "HRD_OK"
     assert info["true_rel_residual"] <= 1e-10
     xg = F.unpack(x, "f64", "even")
-    res = oracle.true_residual_clover(F.U_orc, b_np, xg, m0, csw)
+    res = oracle.true_residual_clover(F.U_orc, b_np, xg, m0, csw, kind)
     assert res <= 1e-10, res
-    xo, _ = oracle.cg_clover(F.U_orc, b_np, m0, csw, tol=1e-12)
+    xo, _ = oracle.cg_clover(F.U_orc, b_np, m0, csw, tol=1e-12, kind=kind)
     assert rel_err(xg, xo) < 1e-7
     if mode == "mixed":
         assert info["reliable_updates"] >= 1
@@ -134,6 +136,18 @@ def test_clover_cg_large(oracle):
     res = oracle.true_residual_clover(F.U_orc, b_np, F.unpack(xm, "f64", "even"), m0, csw)
     assert res <= 1e-10
     assert rel_err(F.unpack(xm, "f64", "even"), F.unpack(x64, "f64", "even")) < 1e-7
+
+
+def test_exp_clover_zero_csw():
+    """c_sw = 0: both kinds give M = m exactly, M^{-1} = 1/m to rounding."""
+    h = hrd()
+    dims, m0 = (4, 4, 4, 4), -0.3
+    F = Field(dims, "fund", seed=91)
+    c = h.clover_build(F.U64, 0.0, m0, dims, "fund", kind="exp")
+    M = h.unpack_clover(c.M, dims, "fund").cpu().numpy()
+    Mi = h.unpack_clover(c.Minv, dims, "fund").cpu().numpy()
+    assert np.all(M == (4.0 + m0) * np.eye(8))
+    assert np.abs(Mi - np.eye(8) / (4.0 + m0)).max() < 1e-16
 
 
 def test_clover_errors():
