@@ -380,3 +380,50 @@ def true_residual_clover(U, b_e, x_e, m0, csw, kind="sw"):
     b_e = restrict(_cplx(b_e), 0)
     Ax = dhat_clover_dagger(U, dhat_clover(U, restrict(_cplx(x_e), 0), m0, csw, Mf), m0, csw, Mf)
     return norm(b_e - Ax) / norm(b_e)
+
+
+# ---------------------------------------------------------------------------
+# 16-bit storage: binary16 spinors with a per-site FP32 scale, binary16 links
+# (the reduced-precision storage of the mixed-precision solver's inner
+# iterations).  The paper does not describe one; this is the definition the
+# GPU library's 16-bit format is tested against, bit for bit.
+# ---------------------------------------------------------------------------
+
+def quantize_spinor16(psi):
+    """Stored form of a spinor field [..., 4, N] (complex): per site, every
+    real part and imaginary part is first rounded to FP32; s is the largest of
+    their absolute values over the site's 4N components (FP32); each is stored
+    as binary16 (round to nearest even) of its FP32 value times the FP32
+    reciprocal 1/s.  A site with s = 0 stores zeros.  Both products and the
+    reciprocal are single FP32 operations.  Returns (codes, s): codes float16
+    [..., 4, N, 2] (re, im), s float32 [...]."""
+    f = np.stack([np.real(psi), np.imag(psi)], axis=-1).astype(np.float32)
+    s = np.abs(f).reshape(f.shape[:-3] + (-1,)).max(axis=-1)
+    safe = np.where(s > 0, s, np.float32(1)).astype(np.float32)
+    inv = np.where(s > 0, np.float32(1) / safe, np.float32(0)).astype(np.float32)
+    codes = (f * inv[..., None, None, None]).astype(np.float16)
+    return codes, s
+
+
+def dequantize_spinor16(codes, s):
+    """The spinor a stored form represents: code * s per real component (an
+    11-bit by 24-bit product, exact in FP64)."""
+    x = codes.astype(np.float64) * s.astype(np.float64)[..., None, None, None]
+    return x[..., 0] + 1j * x[..., 1]
+
+
+def round_spinor16(psi):
+    """psi as stored in the 16-bit format and read back."""
+    return dequantize_spinor16(*quantize_spinor16(psi))
+
+
+def round_links16(U):
+    """Links as stored in the 16-bit format and read back: each real entry (re
+    and im of complex links) rounded to FP32, then to binary16.  Entries of
+    unitary or orthogonal matrices are bounded by 1, so links carry no scale."""
+    def r(a):
+        return np.asarray(a).astype(np.float32).astype(np.float16).astype(np.float64)
+
+    if np.iscomplexobj(U):
+        return r(U.real) + 1j * r(U.imag)
+    return r(U)
