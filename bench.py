@@ -10,7 +10,9 @@ One step = one pass over every stage of the hot path:
   2. the Dslash: R applications of the FP64 hopping block D_eo and of the FP32
      one, timed with HIP events on the library's stream; plain D and the
      even/odd D^ (and dagger) in FP64 and FP32;
-  3. CG on D^+D^ to true residual 1e-10 in FP64 and in mixed precision;
+  3. CG on D^+D^ to true residual 1e-10 in FP64 and in mixed precision
+     (FP32 operator, and 16-bit operator storage: binary16 spinors with a
+     per-site scale and binary16 links);
   4. the fermion-action force from the mixed solution;
   5. a batched 12-right-hand-side FP32 D^ in persistent launches (when the
      library provides it);
@@ -36,10 +38,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "Dslash GB/s & %HBM peak at 48^4 SU(2); mixed vs FP64 CG time to 1e-10"
 
-LINK_BYTES = {("fund", "f64"): 64, ("fund", "f32"): 32, ("adj", "f64"): 72, ("adj", "f32"): 36,
-              ("fund_su2", "f64"): 32, ("fund_su2", "f32"): 16, ("adj_su2", "f64"): 32, ("adj_su2", "f32"): 16}
-SPINOR_BYTES = {("fund", "f64"): 128, ("fund", "f32"): 64, ("adj", "f64"): 192, ("adj", "f32"): 96,
-                ("fund_su2", "f64"): 128, ("fund_su2", "f32"): 64, ("adj_su2", "f64"): 192, ("adj_su2", "f32"): 96}
+LINK_BYTES = {("fund", "f64"): 64, ("fund", "f32"): 32, ("fund", "f16"): 16,
+              ("adj", "f64"): 72, ("adj", "f32"): 36, ("adj", "f16"): 18,
+              ("fund_su2", "f64"): 32, ("fund_su2", "f32"): 16, ("fund_su2", "f16"): 8,
+              ("adj_su2", "f64"): 32, ("adj_su2", "f32"): 16, ("adj_su2", "f16"): 8}
+# F16 spinors: 4N binary16 complex components plus the FP32 site scale
+SPINOR_BYTES = {("fund", "f64"): 128, ("fund", "f32"): 64, ("fund", "f16"): 36,
+                ("adj", "f64"): 192, ("adj", "f32"): 96, ("adj", "f16"): 52,
+                ("fund_su2", "f64"): 128, ("fund_su2", "f32"): 64, ("fund_su2", "f16"): 36,
+                ("adj_su2", "f64"): 192, ("adj_su2", "f32"): 96, ("adj_su2", "f16"): 52}
 
 
 def hop_alg_bytes(V, rep, prec):
@@ -258,6 +265,9 @@ def main():
         src_o = hrd.pack_spinor(psi_nat, dims, "fund", "f64", "odd")
         src_o32 = hrd.convert_spinor(src_o, dims, "fund", 1, True)
         src_e32 = hrd.convert_spinor(src_e, dims, "fund", 1, True)
+        src_o16 = hrd.convert_spinor_prec(src_o, dims, "fund", 1, "f64", "f16")
+        src_e16 = hrd.convert_spinor_prec(src_e, dims, "fund", 1, "f64", "f16")
+        out_e16 = torch.empty_like(src_e16)
         out_e = torch.empty_like(src_e)
         out_e32 = torch.empty_like(src_e32)
         out_all = torch.empty_like(src_all)
@@ -272,22 +282,32 @@ def main():
             dhat64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "eo")
             dhatd64 = hrd.DiracOp(U64, dims, fmt, "f64", m0, "eo", dagger=True)
             dhat32 = hrd.DiracOp(U32, dims, fmt, "f32", m0, "eo")
+            U16 = hrd.convert_gauge_prec(U64, dims, fmt, "f16")
+            hop16 = hrd.DiracOp(U16, dims, fmt, "f16", m0, "hop_eo")
+            dhat16 = hrd.DiracOp(U16, dims, fmt, "f16", m0, "eo")
             r[f"hop_f64_{fmt}"] = timed(lambda: hop64(src_o, out_e), R)
             r[f"hop_f32_{fmt}"] = timed(lambda: hop32(src_o32, out_e32), R)
             r[f"full_f64_{fmt}"] = timed(lambda: full64(src_all, out_all), R // 2)
             r[f"dhat_f64_{fmt}"] = timed(lambda: dhat64(src_e, out_e), R // 2)
             r[f"dhat_dag_f64_{fmt}"] = timed(lambda: dhatd64(src_e, out_e), R // 2)
             r[f"dhat_f32_{fmt}"] = timed(lambda: dhat32(src_e32, out_e32), R // 2)
+            r[f"hop_f16_{fmt}"] = timed(lambda: hop16(src_o16, out_e16), R)
+            r[f"dhat_f16_{fmt}"] = timed(lambda: dhat16(src_e16, out_e16), R // 2)
             # 3. CG solves to 1e-10 (each synchronises internally)
             r[f"cg_f64_{fmt}_ms"], (x64, i64) = timed_once(
                 lambda: hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="f64"))
             r[f"cg_mixed_{fmt}_ms"], (xm, im) = timed_once(
                 lambda: hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="mixed", U32=U32))
-            r[f"cg_f64_{fmt}"], r[f"cg_mixed_{fmt}"] = i64, im
+            r[f"cg_mixed16_{fmt}_ms"], (xh, ih) = timed_once(
+                lambda: hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="mixed16", U32=U16))
+            r[f"cg_f64_{fmt}"], r[f"cg_mixed_{fmt}"], r[f"cg_mixed16_{fmt}"] = i64, im, ih
             n64 = hrd.blas_norm2(x64, dims, fmt, "f64", 1)
             d = xm.clone()
             hrd.blas_axpy(-1.0, x64, d, dims, fmt, "f64", 1)
             r[f"mixed_vs_f64_rel_{fmt}"] = float(np.sqrt(hrd.blas_norm2(d, dims, fmt, "f64", 1) / n64))
+            d = xh.clone()
+            hrd.blas_axpy(-1.0, x64, d, dims, fmt, "f64", 1)
+            r[f"mixed16_vs_f64_rel_{fmt}"] = float(np.sqrt(hrd.blas_norm2(d, dims, fmt, "f64", 1) / n64))
             # 4. fermion force from the mixed solution
             r[f"action_force_{fmt}_ms"], _ = timed_once(lambda: hrd.action_force(U64, xm, m0, dims, fmt))
             # 5. batched multi-RHS D^ (FP32)
@@ -318,7 +338,7 @@ def main():
                                                     clov32=c32))
                     r[f"cg_clover_{kind}_f64"], r[f"cg_clover_{kind}_mixed"] = ic64, icm
                     del c64, c32, cd64, cd32
-            del U64, U32, x64, xm, d
+            del U64, U32, U16, x64, xm, xh, d
         return r
 
     ceiling = copy_ceiling(torch, dev)
@@ -343,7 +363,8 @@ def main():
         per.append(step())
         p = per[-1]
         print(f"[bench] step {s_} done: hop f64 {p['hop_f64_fund']:.3f} ms, cg f64 {p['cg_f64_fund_ms']:.1f} ms, "
-              f"cg mixed {p['cg_mixed_fund_ms']:.1f} ms, cg mixed su2 {p['cg_mixed_fund_su2_ms']:.1f} ms",
+              f"cg mixed {p['cg_mixed_fund_ms']:.1f} ms, cg mixed su2 {p['cg_mixed_fund_su2_ms']:.1f} ms, "
+              f"cg mixed16 su2 {p['cg_mixed16_fund_su2_ms']:.1f} ms",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -355,7 +376,8 @@ def main():
     for fmt in LINK_FORMATS:
         for key, fn, prec in [("hop_f64", hop_alg_bytes, "f64"), ("hop_f32", hop_alg_bytes, "f32"),
                               ("full_f64", full_alg_bytes, "f64"), ("dhat_f64", dhat_alg_bytes, "f64"),
-                              ("dhat_dag_f64", dhat_alg_bytes, "f64"), ("dhat_f32", dhat_alg_bytes, "f32")]:
+                              ("dhat_dag_f64", dhat_alg_bytes, "f64"), ("dhat_f32", dhat_alg_bytes, "f32"),
+                              ("hop_f16", hop_alg_bytes, "f16"), ("dhat_f16", dhat_alg_bytes, "f16")]:
             ms = avg(f"{key}_{fmt}")
             sites = V // 2 if key.startswith("hop") else V
             gbs = fn(V, fmt, prec) / (ms * 1e-3) / 1e9
@@ -367,8 +389,11 @@ def main():
         cg[fmt] = {
             "f64": {"ms": avg(f"cg_f64_{fmt}_ms"), **per[-1][f"cg_f64_{fmt}"]},
             "mixed": {"ms": avg(f"cg_mixed_{fmt}_ms"), **per[-1][f"cg_mixed_{fmt}"]},
+            "mixed16": {"ms": avg(f"cg_mixed16_{fmt}_ms"), **per[-1][f"cg_mixed16_{fmt}"]},
             "mixed_over_f64_time": avg(f"cg_mixed_{fmt}_ms") / avg(f"cg_f64_{fmt}_ms"),
+            "mixed16_over_f64_time": avg(f"cg_mixed16_{fmt}_ms") / avg(f"cg_f64_{fmt}_ms"),
             "mixed_vs_f64_solution_rel_diff": per[-1][f"mixed_vs_f64_rel_{fmt}"],
+            "mixed16_vs_f64_solution_rel_diff": per[-1][f"mixed16_vs_f64_rel_{fmt}"],
             "action_force_ms": avg(f"action_force_{fmt}_ms"),
         }
     clover = {"csw": CSW, "rep": "fund"}

@@ -53,6 +53,20 @@
  *     link FUND_SU2, ADJ_SU2 F64: 2 planes of complex128, entries U00, U01 of
  *                    the fundamental link.
  *     link FUND_SU2, ADJ_SU2 F32: 1 plane of 2 x complex64: (U00, U01).
+ *     spinor, F16 : N planes of 16 B, each 4 components as 8 binary16
+ *                   (re, im, ...) of the component divided by the site
+ *                   scale s, then 1 plane of float32 s (4 B per site).  s is
+ *                   the largest |re| or |im| over the site's components (after
+ *                   rounding them to float32); the stored value is
+ *                   binary16(x * (1/s)) in float32 arithmetic, round to
+ *                   nearest even; s = 0 stores zeros.  The value read back is
+ *                   binary16 * s.  4N * 4 + 4 bytes per site.
+ *     link FUND F16: 1 plane of 8 binary16 (U00, U01, U10, U11 as re, im).
+ *     link ADJ  F16: 1 plane of 8 binary16 (entries 0-7), then 1 plane of
+ *                    binary16 (entry 8).
+ *     link FUND_SU2, ADJ_SU2 F16: 1 plane of 4 binary16 (U00, U01).
+ *     F16 links carry no scale (entries are bounded by 1); each entry is the
+ *     binary16 of its float32 rounding.
  *   A full-lattice spinor is [parity][planes][Vh], even block first.  A
  *   gauge field is [parity][mu][planes][Vh]: block (p, mu) holds the links
  *   U_mu(x) of the sites x of parity p.
@@ -103,7 +117,11 @@ typedef enum {
    (FUND) or cuts by 5/9 (ADJ) the link bytes the operator reads; it assumes
    the links are exactly of SU(2) form. */
 typedef enum { HRD_FUND = 0, HRD_ADJ = 1, HRD_FUND_SU2 = 2, HRD_ADJ_SU2 = 3 } hrd_rep;
-typedef enum { HRD_F64 = 0, HRD_F32 = 1 } hrd_prec;
+/* Storage precision of a field.  HRD_F16 is the 16-bit storage of the mixed
+   solver's inner iterations (binary16 values, FP32 arithmetic; spinors carry
+   a per-site FP32 scale, see PACKED LAYOUTS).  Calls that accept HRD_F16 say
+   so; the others return HRD_EINVAL for it. */
+typedef enum { HRD_F64 = 0, HRD_F32 = 1, HRD_F16 = 2 } hrd_prec;
 
 /* Which block of D a call applies (Sec. 2.1: the plain operator and the
    even/odd preconditioned version). */
@@ -117,7 +135,7 @@ typedef enum {
 /* Which sites a natural-layout spinor transfer covers. */
 typedef enum { HRD_SITES_ALL = 0, HRD_SITES_EVEN = 1, HRD_SITES_ODD = 2 } hrd_sites;
 
-typedef enum { HRD_CG_F64 = 0, HRD_CG_MIXED = 1 } hrd_cg_mode;
+typedef enum { HRD_CG_F64 = 0, HRD_CG_MIXED = 1, HRD_CG_MIXED16 = 2 } hrd_cg_mode;
 
 typedef struct {
     int dims[4]; /* {T, L1, L2, L3} */
@@ -204,6 +222,20 @@ hrd_status hrd_unpack_spinor(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
 hrd_status hrd_convert_spinor(const hrd_lattice *lat, hrd_rep rep, int nparity,
                               int to_f32, const void *in, void *out, void *stream);
 
+/* Spinor storage conversion between any two of HRD_F64, HRD_F32, HRD_F16
+   (nparity = 1 half field, 2 full field; same precision copies).  To F16:
+   each value is rounded to float32 and the site is encoded as stated under
+   PACKED LAYOUTS; from F16 to F64 the stored value binary16 * s is exact,
+   to F32 it is rounded once.  Asynchronous. */
+hrd_status hrd_convert_spinor_prec(const hrd_lattice *lat, hrd_rep rep, int nparity,
+                                   hrd_prec prec_in, hrd_prec prec_out, const void *in,
+                                   void *out, void *stream);
+
+/* Packed FP64 gauge field -> packed HRD_F32 or HRD_F16 copy (F16: each entry
+   binary16 of its float32 rounding).  Asynchronous. */
+hrd_status hrd_convert_gauge_prec(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec_out,
+                                  const void *U64, void *U_out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* The operator (Sec. 2.1: unimproved Wilson-Dirac operator and its even/odd
    preconditioned version).                                                  */
@@ -219,7 +251,8 @@ size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec p
    HOP_EO it is (D_oe)^+, for HOP_OE it is (D_eo)^+).  U is the packed gauge
    field of (rep, prec); psi and out are packed spinors of the sizes the
    parity mode implies; work holds hrd_dirac_workspace_bytes bytes (may be
-   NULL when that is 0).  Asynchronous. */
+   NULL when that is 0).  prec may be HRD_F16 (fields in F16 storage, FP32
+   arithmetic, outputs re-encoded per site).  Asynchronous. */
 hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
                            const void *U, const void *psi, void *out, double m0,
                            hrd_parity parity, int dagger, void *work, void *stream);
@@ -263,15 +296,19 @@ size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode m
 
 /* Solves A x = b.  b and x are packed FP64 even half fields; x holds the
    initial guess on entry (zero it for x0 = 0) and the solution on exit.
-   U64 is the packed FP64 gauge field; U32 its packed FP32 copy (required for
-   HRD_CG_MIXED, ignored for HRD_CG_F64).  Stops when the true relative
-   residual ||b - A x|| / ||b||, recomputed in FP64, is <= tol.
-     HRD_CG_F64   : every vector and reduction in FP64.
-     HRD_CG_MIXED : iterations in FP32 (operator, r, p, A p), FP64 solution
-                    accumulation and reductions, and a reliable update (FP64
-                    recomputation of the residual) whenever the iterated
-                    residual drops below delta times its largest value since
-                    the last update (delta <= 0 selects 0.1).
+   U64 is the packed FP64 gauge field; U32 its packed reduced-precision copy:
+   FP32 for HRD_CG_MIXED, F16 for HRD_CG_MIXED16 (hrd_convert_gauge_prec),
+   ignored for HRD_CG_F64.  Stops when the true relative residual
+   ||b - A x|| / ||b||, recomputed in FP64, is <= tol.
+     HRD_CG_F64     : every vector and reduction in FP64.
+     HRD_CG_MIXED   : iterations in FP32 (operator, r, p, A p), FP64 solution
+                      accumulation and reductions, and a reliable update (FP64
+                      recomputation of the residual) whenever the iterated
+                      residual drops below delta times its largest value since
+                      the last update (delta <= 0 selects 0.1).
+     HRD_CG_MIXED16 : as HRD_CG_MIXED with the operator's fields (p, the odd
+                      intermediate, D^ p) and the links in F16 storage (FP32
+                      arithmetic); the iterated residual stays FP32.
    maxiter bounds the iterations.  info (may be NULL) is filled in every case.
    Synchronises the stream.  Returns HRD_ENOCONV if the tolerance is not
    reached, HRD_EBREAKDOWN on <p, A p> <= 0 or a non-finite residual. */
@@ -322,6 +359,7 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind
                             const void *U64, double csw, double m0, void *M64,
                             void *Minv64, void *stream);
 
+/* (see also hrd_convert_spinor_prec / hrd_convert_gauge_prec for F16) */
 /* FP64 -> FP32 copy of a packed clover field (for the mixed-precision CG
    and FP32 operators).  Asynchronous. */
 hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64,
@@ -336,7 +374,8 @@ hrd_status hrd_unpack_clover(const hrd_lattice *lat, hrd_rep rep, const void *C6
 /* out = D_sw psi (HRD_FULL, full-lattice fields) or out_e = D^_sw psi_e
    (HRD_EO, even half fields; needs Minv and a workspace of
    hrd_dirac_workspace_bytes(HRD_EO) bytes); dagger != 0 applies the adjoint.
-   U, M, Minv, psi and out share the precision prec.  The off-diagonal blocks
+   U, M, Minv, psi and out share the precision prec, except for HRD_F16
+   (F16 U, psi and out) where M and Minv are FP32.  The off-diagonal blocks
    D_eo, D_oe carry no clover term: apply them with hrd_dirac_apply
    (HRD_HOP_EO, HRD_HOP_OE gives HRD_EINVAL here).  The mass is the one built
    into M.  Asynchronous. */
@@ -347,8 +386,8 @@ hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec 
 
 /* CG on A = D^_sw^+ D^_sw, as hrd_cg_solve (same workspace size, same modes,
    tolerance, reliable updates, info and errors), with the FP64 clover fields
-   M64, Minv64 and, for HRD_CG_MIXED, their FP32 copies M32, Minv32
-   (ignored for HRD_CG_F64). */
+   M64, Minv64 and, for HRD_CG_MIXED and HRD_CG_MIXED16, their FP32 copies
+   M32, Minv32 (ignored for HRD_CG_F64). */
 hrd_status hrd_cg_solve_clover(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
                                const void *U64, const void *U32, const void *M64,
                                const void *Minv64, const void *M32, const void *Minv32,

@@ -47,6 +47,12 @@ hrd_status check_lattice(const hrd_lattice *lat)
     return HRD_OK;
 }
 
+hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec)
+{
+    if (prec == HRD_F16) return check_rep_prec(rep, HRD_F64);
+    return check_rep_prec(rep, prec);
+}
+
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
 {
     if (rep < HRD_FUND || rep > HRD_ADJ_SU2) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
@@ -198,10 +204,10 @@ hrd_status read_scalars(const double *sc_dev, double *host, hipStream_t st)
 }
 
 struct CgBuffers {
-    // FP64 (both modes)
+    // FP64 (every mode)
     void *r64, *p64, *q64, *Ap64, *t64;
-    // FP32 (mixed)
-    void *r32, *p32, *q32, *Ap32, *t32;
+    // mixed modes: r32 is FP32; p, q, t are FP32 (MIXED) or F16 (MIXED16)
+    void *r32, *plo, *qlo, *tlo;
     double *partials, *sc;
 };
 
@@ -220,11 +226,11 @@ size_t carve_cg(const hrd_lattice *lat, int rep, int mode, void *work, CgBuffers
     if (mode == HRD_CG_F64) {
         t.p64 = c.take(h64);
     } else {
+        const size_t hlo = mode == HRD_CG_MIXED16 ? spinor_bytes(lat, rep, HRD_F16, 1) : h32;
         t.r32 = c.take(h32);
-        t.p32 = c.take(h32);
-        t.q32 = c.take(h32);
-        t.Ap32 = c.take(h32);
-        t.t32 = c.take(h32);
+        t.plo = c.take(hlo);
+        t.qlo = c.take(hlo);
+        t.tlo = c.take(hlo);
     }
     t.partials = (double *)c.take(sizeof(double) * nparts);
     t.sc = (double *)c.take(sizeof(double) * S_COUNT);
@@ -242,13 +248,14 @@ const char *hrd_version(void) { return "hrd 0.1 (gfx950)"; }
 
 size_t hrd_spinor_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK || (nparity != 1 && nparity != 2)) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec_any(rep, prec) != HRD_OK || (nparity != 1 && nparity != 2))
+        return 0;
     return spinor_bytes(lat, rep, prec, nparity);
 }
 
 size_t hrd_gauge_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec_any(rep, prec) != HRD_OK) return 0;
     return gauge_bytes(lat, rep, prec);
 }
 
@@ -354,9 +361,40 @@ hrd_status hrd_convert_spinor(const hrd_lattice *lat, hrd_rep rep, int nparity, 
                      "convert_spinor launch");
 }
 
+hrd_status hrd_convert_spinor_prec(const hrd_lattice *lat, hrd_rep rep, int nparity, hrd_prec prec_in,
+                                   hrd_prec prec_out, const void *in, void *out, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec_any(rep, prec_in));
+    HRD_TRY(check_rep_prec_any(rep, prec_out));
+    if (nparity != 1 && nparity != 2) return fail(HRD_EINVAL, "nparity must be 1 or 2");
+    if (!in || !out) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(in, spinor_bytes(lat, rep, prec_in, nparity), out, spinor_bytes(lat, rep, prec_out, nparity)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_convert_spinor_prec(rep, g.Vh, nparity, prec_in, prec_out, in, out, (hipStream_t)stream),
+                     "convert_spinor_prec launch");
+}
+
+hrd_status hrd_convert_gauge_prec(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec_out, const void *U64,
+                                  void *U_out, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_rep_prec_any(rep, prec_out));
+    if (prec_out == HRD_F64) return fail(HRD_EINVAL, "prec_out must be HRD_F32 or HRD_F16");
+    if (!U64 || !U_out) return fail(HRD_EINVAL, "NULL field pointer");
+    if (overlap(U64, gauge_bytes(lat, rep, HRD_F64), U_out, gauge_bytes(lat, rep, prec_out)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    const hipStream_t st = (hipStream_t)stream;
+    return check_hip(prec_out == HRD_F32 ? launch_convert_gauge(rep, g, U64, U_out, st)
+                                         : launch_convert_gauge_h16(rep, g, U64, U_out, st),
+                     "convert_gauge_prec launch");
+}
+
 size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, hrd_parity parity)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec_any(rep, prec) != HRD_OK) return 0;
     return parity == HRD_EO ? spinor_bytes(lat, rep, prec, 1) : 0;
 }
 
@@ -364,7 +402,7 @@ hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
                            void *out, double m0, hrd_parity parity, int dagger, void *work, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_rep_prec(rep, prec));
+    HRD_TRY(check_rep_prec_any(rep, prec));
     if (parity < HRD_FULL || parity > HRD_HOP_OE) return fail(HRD_EINVAL, "invalid parity mode %d", (int)parity);
     if (!U || !psi || !out) return fail(HRD_EINVAL, "NULL field pointer");
     if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return fail(HRD_EINVAL, "m0 = %g is not finite or makes 4 + m0 zero", m0);
@@ -443,7 +481,7 @@ hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec 
                                   void *work, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_rep_prec(rep, prec));
+    HRD_TRY(check_rep_prec_any(rep, prec));
     if (parity != HRD_FULL && parity != HRD_EO)
         return fail(HRD_EINVAL, "clover operator supports HRD_FULL and HRD_EO (hop blocks are those of hrd_dirac_apply)");
     if (!U || !M || !psi || !out) return fail(HRD_EINVAL, "NULL field pointer");
@@ -451,7 +489,7 @@ hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec 
     const int np = parity == HRD_FULL ? 2 : 1;
     const size_t sb = spinor_bytes(lat, rep, prec, np);
     const size_t ub = gauge_bytes(lat, rep, prec);
-    const size_t cb = clover_bytes(lat, rep, prec);
+    const size_t cb = clover_bytes(lat, rep, prec == HRD_F16 ? HRD_F32 : prec);
     if (overlap(out, sb, psi, sb) || overlap(out, sb, U, ub) || overlap(out, sb, M, cb) ||
         overlap(out, sb, Minv, cb))
         return fail(HRD_EALIAS, "output overlaps an input");
@@ -546,7 +584,7 @@ hrd_status hrd_blas_xpay(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int
 size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode)
 {
     if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK) return 0;
-    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED) return 0;
+    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED && mode != HRD_CG_MIXED16) return 0;
     return carve_cg(lat, rep, mode, nullptr, nullptr);
 }
 
@@ -568,12 +606,14 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
         if (s == HRD_OK) s = check_rep_prec(rep, HRD_F64);
         if (s != HRD_OK) return finish(s);
     }
-    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED) return finish(fail(HRD_EINVAL, "invalid CG mode %d", (int)mode));
+    if (mode != HRD_CG_F64 && mode != HRD_CG_MIXED && mode != HRD_CG_MIXED16)
+        return finish(fail(HRD_EINVAL, "invalid CG mode %d", (int)mode));
     if (!U64 || !b || !x || !work) return finish(fail(HRD_EINVAL, "NULL pointer"));
-    if (mode == HRD_CG_MIXED && !U32) return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 gauge field"));
+    if (mode != HRD_CG_F64 && !U32)
+        return finish(fail(HRD_EINVAL, "mixed CG needs the reduced-precision gauge field (FP32 or F16)"));
     if (!cl64 && (!std::isfinite(m0) || 4.0 + m0 == 0.0)) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
     if (cl64 && (!cl64->M || !cl64->Minv)) return finish(fail(HRD_EINVAL, "NULL FP64 clover field"));
-    if (cl64 && mode == HRD_CG_MIXED && (!cl32 || !cl32->M || !cl32->Minv))
+    if (cl64 && mode != HRD_CG_F64 && (!cl32 || !cl32->M || !cl32->Minv))
         return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 clover fields"));
     if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(HRD_EINVAL, "tol must be positive"));
     if (maxiter < 0) return finish(fail(HRD_EINVAL, "maxiter must be >= 0"));
@@ -588,7 +628,7 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
         const size_t c64 = clover_bytes(lat, rep, HRD_F64), c32 = clover_bytes(lat, rep, HRD_F32);
         bool bad = overlap(work, need, cl64->M, c64) || overlap(work, need, cl64->Minv, c64) ||
                    overlap(x, h64, cl64->M, c64) || overlap(x, h64, cl64->Minv, c64);
-        if (mode == HRD_CG_MIXED)
+        if (mode != HRD_CG_F64)
             bad = bad || overlap(work, need, cl32->M, c32) || overlap(work, need, cl32->Minv, c32) ||
                   overlap(x, h64, cl32->M, c32) || overlap(x, h64, cl32->Minv, c32);
         if (bad) return finish(fail(HRD_EALIAS, "a clover field overlaps x or the workspace"));
@@ -689,14 +729,17 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
                            inf.true_rel_residual));
     }
 
-    // mixed precision with reliable updates
+    // mixed precision with reliable updates; the operator's fields are FP32
+    // (MIXED) or F16 (MIXED16), the iterated residual r32 is FP32 in both
+    const int lp = mode == HRD_CG_MIXED16 ? HRD_F16 : HRD_F32;
     const size_t h32 = spinor_bytes(lat, rep, HRD_F32, 1);
-    CG_HIP(launch_copy(h32, w.r32, w.p32, st), "copy");
+    if (lp == HRD_F32) CG_HIP(launch_copy(h32, w.r32, w.plo, st), "copy");
+    else CG_HIP(launch_convert_spinor_prec(rep, g.Vh, 1, HRD_F32, HRD_F16, w.r32, w.plo, st), "p = r");
     double rmax = std::sqrt(rr);
     while (inf.iters < maxiter) {
-        CG_HIP(apply_dhat(rep, HRD_F32, g, U32, w.p32, w.q32, w.t32, m0, false, w.partials, st, cl32), "D^ p");
+        CG_HIP(apply_dhat(rep, lp, g, U32, w.plo, w.qlo, w.tlo, m0, false, w.partials, st, cl32), "D^ p");
         CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
-        CG_HIP(apply_dhat_dag_update_r(rep, HRD_F32, g, U32, w.q32, w.r32, w.t32, m0, w.sc, w.partials, st, cl32),
+        CG_HIP(apply_dhat_dag_update_r(rep, lp, g, U32, w.qlo, w.r32, w.tlo, m0, w.sc, w.partials, st, cl32),
                "r -= alpha D^+ q");
         CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
         inf.iters++;
@@ -712,7 +755,8 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
         rmax = std::max(rmax, rnew);
         if (rnew < delta * rmax || rnew <= target) {
             // x += alpha p ; then r = b - A x in FP64, r32 = f32(r), beta from the new residual
-            CG_HIP(launch_cg_update_x_mixed(g.Vh, nc, x, w.p32, w.sc, st), "update x");
+            if (lp == HRD_F32) CG_HIP(launch_cg_update_x_mixed(g.Vh, nc, x, w.plo, w.sc, st), "update x");
+            else CG_HIP(launch_cg_update_x_h16(g.Vh, nc, x, w.plo, w.sc, st), "update x");
             hrd_status s = true_residual();
             if (s != HRD_OK) return finish(s);
             inf.reliable_updates++;
@@ -721,9 +765,11 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
             if (!std::isfinite(rt)) return finish(fail(HRD_EBREAKDOWN, "non-finite residual"));
             if (rt <= target) return finish(HRD_OK);
             rmax = rt;
-            CG_HIP(launch_cg_update_p32(n32, w.p32, w.r32, w.sc, st), "update p");
+            if (lp == HRD_F32) CG_HIP(launch_cg_update_p32(n32, w.plo, w.r32, w.sc, st), "update p");
+            else CG_HIP(launch_cg_update_p16(g.Vh, nc, w.plo, w.r32, w.sc, st), "update p");
         } else {
-            CG_HIP(launch_cg_update_xp_mixed(g.Vh, nc, x, w.p32, w.r32, w.sc, st), "update x, p");
+            if (lp == HRD_F32) CG_HIP(launch_cg_update_xp_mixed(g.Vh, nc, x, w.plo, w.r32, w.sc, st), "update x, p");
+            else CG_HIP(launch_cg_update_xp_h16(g.Vh, nc, x, w.plo, w.r32, w.sc, st), "update x, p");
         }
     }
     {

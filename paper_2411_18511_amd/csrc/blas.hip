@@ -437,4 +437,66 @@ hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st)
     return hipGetLastError();
 }
 
+namespace {
+
+// Mixed CG with p in F16 storage: one thread per site (the F16 site scale
+// covers all components of the site).  MODE 0: x += alpha p, p = r + beta p;
+// MODE 1: x += alpha p; MODE 2: p = r + (rr / rr_old) p.
+template <int NC, int MODE>
+__global__ __launch_bounds__(kBlock) void cg_update_h16_kernel(int Vh, void *x64, void *p16, const void *r32,
+                                                               const double *sc)
+{
+    const int site = blockIdx.x * kBlock + threadIdx.x;
+    if (site >= Vh) return;
+    Cx<float> p[NC];
+    SpinorIO<h16>::load<NC>(p16, Vh, site, p);
+    if constexpr (MODE != 2) {
+        const double alpha = sc[S_ALPHA];
+        Cx<double> x[NC];
+        SpinorIO<double>::load<NC>(x64, Vh, site, x);
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            x[k].re += alpha * (double)p[k].re;
+            x[k].im += alpha * (double)p[k].im;
+        }
+        SpinorIO<double>::store<NC>(x64, Vh, site, x);
+    }
+    if constexpr (MODE != 1) {
+        const float beta = MODE == 0 ? (float)sc[S_BETA] : (float)(sc[S_RROLD] > 0.0 ? sc[S_RR] / sc[S_RROLD] : 0.0);
+        Cx<float> r[NC];
+        SpinorIO<float>::load<NC>(r32, Vh, site, r);
+#pragma unroll
+        for (int k = 0; k < NC; k++) p[k] = Cx<float>{r[k].re + beta * p[k].re, r[k].im + beta * p[k].im};
+        SpinorIO<h16>::store<NC>(p16, Vh, site, p);
+    }
+}
+
+template <int MODE>
+hipError_t launch_h16_update(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
+                             hipStream_t st)
+{
+    const dim3 grid((unsigned)((Vh + kBlock - 1) / kBlock));
+    if (ncomp == 8) hipLaunchKernelGGL((cg_update_h16_kernel<8, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc);
+    else hipLaunchKernelGGL((cg_update_h16_kernel<12, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cg_update_xp_h16(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
+                                   hipStream_t st)
+{
+    return launch_h16_update<0>(Vh, ncomp, x64, p16, r32, sc, st);
+}
+
+hipError_t launch_cg_update_x_h16(int Vh, int ncomp, void *x64, const void *p16, const double *sc, hipStream_t st)
+{
+    return launch_h16_update<1>(Vh, ncomp, x64, const_cast<void *>(p16), nullptr, sc, st);
+}
+
+hipError_t launch_cg_update_p16(int Vh, int ncomp, void *p16, const void *r32, const double *sc, hipStream_t st)
+{
+    return launch_h16_update<2>(Vh, ncomp, nullptr, p16, r32, sc, st);
+}
+
 }  // namespace hrd

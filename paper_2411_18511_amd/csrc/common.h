@@ -247,6 +247,50 @@ template <typename R>
 __device__ __forceinline__ Cx<R> mul_i(Cx<R> a) { return {-a.im, a.re}; }
 
 // ---------------------------------------------------------------------------
+// Storage types.  A field's storage type S is double (F64), float (F32) or h16
+// (F16: binary16 values); arithmetic runs in Arith<S>::type (FP32 for h16).
+// ---------------------------------------------------------------------------
+struct h16 {};
+template <typename S>
+struct Arith {
+    using type = S;
+};
+template <>
+struct Arith<h16> {
+    using type = float;
+};
+
+typedef _Float16 vh8 __attribute__((ext_vector_type(8)));
+typedef _Float16 vh4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ vh8 ld16h(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vh8 *>(p));
+    else return *reinterpret_cast<const vh8 *>(p);
+}
+template <bool NT>
+__device__ __forceinline__ void st16h(void *p, vh8 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<vh8 *>(p));
+    else *reinterpret_cast<vh8 *>(p) = v;
+}
+template <bool NT>
+__device__ __forceinline__ vh4 ld8h(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const vh4 *>(p));
+    else return *reinterpret_cast<const vh4 *>(p);
+}
+template <typename T>
+__device__ __forceinline__ T ld_scalar(const T *p, bool nt)
+{
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+// binary16 of the FP32 rounding of x (round to nearest even at both steps)
+template <typename T>
+__device__ __forceinline__ _Float16 to_h16(T x) { return (_Float16)(float)x; }
+
+// ---------------------------------------------------------------------------
 // Packed spinor planes: F64 one complex128 per 16-byte element, F32 two
 // complex64 per 16-byte element (components 2k, 2k+1 in plane k).
 // ---------------------------------------------------------------------------
@@ -297,6 +341,62 @@ struct SpinorIO<float> {
     }
 };
 
+// F16: NC/4 planes of 16-byte elements, each holding four components as eight
+// binary16 (re, im, re, im, ...) divided by the site scale s, followed by one
+// plane of FP32 s (4 bytes per site).  s is the largest |re| or |im| of the
+// site; the stored values are binary16(x * (1/s)) with FP32 x, and a site with
+// s = 0 stores zeros.  Reading gives binary16 * s in FP32.
+template <>
+struct SpinorIO<h16> {
+    template <int NC, bool NT = false>
+    __device__ __forceinline__ static void load(const void *base, int Vh, int site, Cx<float> (&c)[NC])
+    {
+        const char *p = reinterpret_cast<const char *>(base);
+        const float s = ld_scalar(reinterpret_cast<const float *>(p + (size_t)(NC / 4) * Vh * 16) + site, NT);
+#pragma unroll
+        for (int k = 0; k < NC / 4; k++) {
+            const vh8 v = ld16h<NT>(p + ((size_t)k * Vh + site) * 16);
+#pragma unroll
+            for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<float>{(float)v[2 * j] * s, (float)v[2 * j + 1] * s};
+        }
+    }
+    // the stored value exactly (binary16 * s in FP64), for conversions to F64
+    template <int NC>
+    __device__ __forceinline__ static void load_exact(const void *base, int Vh, int site, Cx<double> (&c)[NC])
+    {
+        const char *p = reinterpret_cast<const char *>(base);
+        const double s = reinterpret_cast<const float *>(p + (size_t)(NC / 4) * Vh * 16)[site];
+#pragma unroll
+        for (int k = 0; k < NC / 4; k++) {
+            const vh8 v = ld16h<false>(p + ((size_t)k * Vh + site) * 16);
+#pragma unroll
+            for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<double>{(double)v[2 * j] * s, (double)v[2 * j + 1] * s};
+        }
+    }
+    template <int NC, bool NT = false>
+    __device__ __forceinline__ static void store(void *base, int Vh, int site, const Cx<float> (&c)[NC])
+    {
+        char *p = reinterpret_cast<char *>(base);
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NC; k++) m = fmaxf(m, fmaxf(fabsf(c[k].re), fabsf(c[k].im)));
+        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+        for (int k = 0; k < NC / 4; k++) {
+            vh8 v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                v[2 * j] = (_Float16)(c[4 * k + j].re * inv);
+                v[2 * j + 1] = (_Float16)(c[4 * k + j].im * inv);
+            }
+            st16h<NT>(p + ((size_t)k * Vh + site) * 16, v);
+        }
+        float *sp = reinterpret_cast<float *>(p + (size_t)(NC / 4) * Vh * 16) + site;
+        if constexpr (NT) __builtin_nontemporal_store(m, sp);
+        else *sp = m;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Packed links.  Block (parity p, direction mu) starts at byte
 // (4 p + mu) * Vh * bytes_per_link.
@@ -322,15 +422,17 @@ __host__ __device__ constexpr int ncolour(int rep) { return (rep == HRD_FUND || 
 // links uses: FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2.
 __host__ __device__ constexpr int base_rep(int rep) { return ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ; }
 
+// Bytes per link: real entries (8 FUND, 9 ADJ, 4 for a first row) times the
+// storage width (8 F64, 4 F32, 2 F16).
 __host__ __device__ constexpr int link_bytes(int rep, int prec)
 {
-    return is_su2_row(rep) ? (prec == HRD_F64 ? 32 : 16)
-                           : rep == HRD_FUND ? (prec == HRD_F64 ? 64 : 32) : (prec == HRD_F64 ? 72 : 36);
+    return (is_su2_row(rep) ? 4 : rep == HRD_FUND ? 8 : 9) * (prec == HRD_F64 ? 8 : prec == HRD_F32 ? 4 : 2);
 }
 
+// Bytes per site of a spinor: 4N complex components; F16 adds the FP32 site scale.
 __host__ __device__ constexpr int spinor_site_bytes(int rep, int prec)
 {
-    return 4 * ncolour(rep) * (prec == HRD_F64 ? 16 : 8);
+    return prec == HRD_F16 ? 4 * ncolour(rep) * 4 + 4 : 4 * ncolour(rep) * (prec == HRD_F64 ? 16 : 8);
 }
 
 template <>
@@ -498,26 +600,107 @@ struct RowIO<float> {
     }
 };
 
+// F16 links: binary16 entries, no scale (entries of unitary and orthogonal
+// matrices are bounded by 1).  FUND: one 16-byte plane (U00, U01, U10, U11 as
+// re, im).  ADJ: a 16-byte plane with entries 0-7 and a 2-byte plane with
+// entry 8.  First row: one 8-byte plane (U00, U01).
+template <>
+struct LinkIO<HRD_FUND, h16> {
+    using Link = FundLink<float>;
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 16;
+        const vh8 v = ld16h<NT>(b + (size_t)site * 16);
+        Link l;
+#pragma unroll
+        for (int e = 0; e < 4; e++) l.u[e >> 1][e & 1] = Cx<float>{(float)v[2 * e], (float)v[2 * e + 1]};
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const FundLink<T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 16;
+        vh8 v;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            v[2 * e] = to_h16(l.u[e >> 1][e & 1].re);
+            v[2 * e + 1] = to_h16(l.u[e >> 1][e & 1].im);
+        }
+        st16h<false>(b + (size_t)site * 16, v);
+    }
+};
+
+template <>
+struct LinkIO<HRD_ADJ, h16> {
+    using Link = AdjLink<float>;
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 18;
+        const vh8 v = ld16h<NT>(blk + (size_t)site * 16);
+        const _Float16 e8 = ld_scalar(reinterpret_cast<const _Float16 *>(blk + (size_t)Vh * 16) + site, NT);
+        Link l;
+#pragma unroll
+        for (int k = 0; k < 8; k++) l.r[k / 3][k % 3] = (float)v[k];
+        l.r[2][2] = (float)e8;
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const AdjLink<T> &l)
+    {
+        char *blk = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 18;
+        vh8 v;
+#pragma unroll
+        for (int k = 0; k < 8; k++) v[k] = to_h16(l.r[k / 3][k % 3]);
+        st16h<false>(blk + (size_t)site * 16, v);
+        reinterpret_cast<_Float16 *>(blk + (size_t)Vh * 16)[site] = to_h16(l.r[2][2]);
+    }
+};
+
+template <>
+struct RowIO<h16> {
+    template <bool NT = false>
+    __device__ __forceinline__ static Su2Row<float> load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 8;
+        const vh4 v = ld8h<NT>(b + (size_t)site * 8);
+        return Su2Row<float>{{(float)v[0], (float)v[1]}, {(float)v[2], (float)v[3]}};
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Su2Row<T> &r)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 8;
+        vh4 v;
+        v[0] = to_h16(r.a.re);
+        v[1] = to_h16(r.a.im);
+        v[2] = to_h16(r.b.re);
+        v[3] = to_h16(r.b.im);
+        *reinterpret_cast<vh4 *>(b + (size_t)site * 8) = v;
+    }
+};
+
 template <typename R>
 struct LinkIO<HRD_FUND_SU2, R> {
-    using Link = FundLink<R>;
+    using Link = FundLink<typename Arith<R>::type>;
     // second row reconstructed: U10 = -conj(U01), U11 = conj(U00)
     template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
-        const Su2Row<R> r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
+        const auto r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
         Link l;
         l.u[0][0] = r.a;
         l.u[0][1] = r.b;
-        l.u[1][0] = Cx<R>{-r.b.re, r.b.im};
-        l.u[1][1] = Cx<R>{r.a.re, -r.a.im};
+        l.u[1][0] = {-r.b.re, r.b.im};
+        l.u[1][1] = {r.a.re, -r.a.im};
         return l;
     }
 };
 
 template <typename R>
 struct LinkIO<HRD_ADJ_SU2, R> {
-    using Link = AdjLink<R>;
+    using A = typename Arith<R>::type;
+    using Link = AdjLink<A>;
     // R(U)_ij = (a0^2 - |v|^2) d_ij + 2 v_i v_j + 2 a0 eps_ijk v_k for
     // U = a0 + i (v1 s1 + v2 s2 + v3 s3), read from the first row
     // a = a0 + i v3, b = v2 + i v1; this equals tr(s_i U s_j U^+) / 2 for
@@ -525,10 +708,10 @@ struct LinkIO<HRD_ADJ_SU2, R> {
     template <bool NT = false>
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
-        const Su2Row<R> r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
-        const R a0 = r.a.re, v0 = r.b.im, v1 = r.b.re, v2 = r.a.im;
-        const R d = a0 * a0 - (v0 * v0 + v1 * v1 + v2 * v2);
-        const R t0 = 2 * a0 * v0, t1 = 2 * a0 * v1, t2 = 2 * a0 * v2;
+        const auto r = RowIO<R>::template load<NT>(U, Vh, p, mu, site);
+        const A a0 = r.a.re, v0 = r.b.im, v1 = r.b.re, v2 = r.a.im;
+        const A d = a0 * a0 - (v0 * v0 + v1 * v1 + v2 * v2);
+        const A t0 = 2 * a0 * v0, t1 = 2 * a0 * v1, t2 = 2 * a0 * v2;
         Link l;
         l.r[0][0] = d + 2 * v0 * v0;
         l.r[1][1] = d + 2 * v1 * v1;

@@ -55,7 +55,8 @@ int choose_slab(const int dims[4])
 
 namespace {
 
-template <int MU, bool DAG, int REP, typename R>
+// S: storage type of the source spinor and the links; R: arithmetic type.
+template <int MU, bool DAG, int REP, typename S, typename R = typename Arith<S>::type>
 __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, int p, const void *U,
                                         const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
 {
@@ -63,8 +64,8 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
     constexpr int NC = 4 * N;
     constexpr int SF = DAG ? +1 : -1;  // forward term uses (1 + SF g_mu)
     constexpr int SB = -SF;            // backward term uses (1 + SB g_mu)
-    using IO = SpinorIO<R>;
-    using LIO = LinkIO<REP, R>;
+    using IO = SpinorIO<S>;
+    using LIO = LinkIO<REP, S>;
     {
         const int j = nbr_fwd(g, s, MU);
         Cx<R> psi[NC];
@@ -106,9 +107,13 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 // out = a psi_self(x) + b (H psi_src)(x) on the target parity; FULL runs both
 // parities in one launch (blocks alternate parity), NORM writes one partial
 // of ||out||^2 per block.  CLOV selects a clover epilogue (CloverMode).
-template <int REP, typename R, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE>
+// S is the storage type of the operator's spinors and links (double, float or
+// h16), R = Arith<S>::type the arithmetic; the residual of the RUPD epilogue
+// and the clover fields are stored in R.
+template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE>
 __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
 {
+    using R = typename Arith<S>::type;
     constexpr int N = NCol<REP>::value;
     constexpr int NC = 4 * N;
     const Geom &g = a.g;
@@ -138,10 +143,10 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
         Cx<R> acc[NC];
 #pragma unroll
         for (int k = 0; k < NC; k++) acc[k] = Cx<R>{0, 0};
-        hop_dir<0, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
-        hop_dir<1, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
-        hop_dir<2, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
-        hop_dir<3, DAG, REP, R>(g, s, idx, p, a.U, src, acc);
+        hop_dir<0, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+        hop_dir<1, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+        hop_dir<2, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+        hop_dir<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         const R cb = (R)a.b;
         Cx<R> out[NC];
         if constexpr (CLOV == CLOV_INV) {
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, t, out);
         } else if constexpr (HAS_A && CLOV == CLOV_SELF) {
             Cx<R> self_v[NC], ms[NC];
-            SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
+            SpinorIO<S>::template load<NC>(self, g.Vh, idx, self_v);
             clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, self_v, ms);
 #pragma unroll
             for (int k = 0; k < NC; k++)
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
         } else if constexpr (HAS_A) {
             const R ca = (R)a.a;
             Cx<R> self_v[NC];
-            SpinorIO<R>::template load<NC>(self, g.Vh, idx, self_v);
+            SpinorIO<S>::template load<NC>(self, g.Vh, idx, self_v);
 #pragma unroll
             for (int k = 0; k < NC; k++) out[k] = axpby(ca, self_v[k], cb, acc[k]);
         } else {
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             }
             SpinorIO<R>::template store<NC, HRD_NT_STORE>(a.r, g.Vh, idx, rv);
         } else {
-            SpinorIO<R>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
+            SpinorIO<S>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
             if constexpr (NORM) {
 #pragma unroll
                 for (int k = 0; k < NC; k++)
@@ -192,13 +197,13 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
     }
 }
 
-template <int REP, typename R, int CLOV>
+template <int REP, typename S, int CLOV>
 hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
 {
     const int nb = hop_blocks(a.g) * (full ? 2 : 1);
     const dim3 grid(nb), block(kHopBlock);
 #define HRD_LAUNCH(D, A, NR, F) \
-    hipLaunchKernelGGL((hop_kernel<REP, R, D, A, NR, F, false, CLOV>), grid, block, 0, st, a)
+    hipLaunchKernelGGL((hop_kernel<REP, S, D, A, NR, F, false, CLOV>), grid, block, 0, st, a)
     if constexpr (CLOV == CLOV_INV) {
         // M^{-1} (b H src): no self term, no norm
         if (dag) HRD_LAUNCH(true, false, false, false);
@@ -240,26 +245,48 @@ hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool 
     return hipGetLastError();
 }
 
-template <int REP, typename R>
+template <int REP, typename S>
 hipError_t dispatch_hop_clov(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st, int clov)
 {
     switch (clov) {
-        case CLOV_SELF: return dispatch_hop<REP, R, CLOV_SELF>(a, dag, has_a, norm, full, st);
-        case CLOV_INV: return dispatch_hop<REP, R, CLOV_INV>(a, dag, has_a, norm, full, st);
-        default: return dispatch_hop<REP, R, CLOV_NONE>(a, dag, has_a, norm, full, st);
+        case CLOV_SELF: return dispatch_hop<REP, S, CLOV_SELF>(a, dag, has_a, norm, full, st);
+        case CLOV_INV: return dispatch_hop<REP, S, CLOV_INV>(a, dag, has_a, norm, full, st);
+        default: return dispatch_hop<REP, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
     }
 }
 
-template <int REP, typename R>
+template <int REP, typename S>
 hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st, int clov)
 {
     if (clov == CLOV_SELF)
-        hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true, CLOV_SELF>), dim3(hop_blocks(a.g)),
+        hipLaunchKernelGGL((hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>), dim3(hop_blocks(a.g)),
                            dim3(kHopBlock), 0, st, a);
     else
-        hipLaunchKernelGGL((hop_kernel<REP, R, true, true, true, false, true>), dim3(hop_blocks(a.g)),
+        hipLaunchKernelGGL((hop_kernel<REP, S, true, true, true, false, true>), dim3(hop_blocks(a.g)),
                            dim3(kHopBlock), 0, st, a);
     return hipGetLastError();
+}
+
+template <typename S>
+hipError_t rupd_for(int rep, const HopArgs &a, hipStream_t st, int clov)
+{
+    switch (rep) {
+        case HRD_FUND: return dispatch_rupd<HRD_FUND, S>(a, st, clov);
+        case HRD_ADJ: return dispatch_rupd<HRD_ADJ, S>(a, st, clov);
+        case HRD_FUND_SU2: return dispatch_rupd<HRD_FUND_SU2, S>(a, st, clov);
+        default: return dispatch_rupd<HRD_ADJ_SU2, S>(a, st, clov);
+    }
+}
+
+template <typename S>
+hipError_t hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st, int clov)
+{
+    switch (rep) {
+        case HRD_FUND: return dispatch_hop_clov<HRD_FUND, S>(a, dag, has_a, norm, full, st, clov);
+        case HRD_ADJ: return dispatch_hop_clov<HRD_ADJ, S>(a, dag, has_a, norm, full, st, clov);
+        case HRD_FUND_SU2: return dispatch_hop_clov<HRD_FUND_SU2, S>(a, dag, has_a, norm, full, st, clov);
+        default: return dispatch_hop_clov<HRD_ADJ_SU2, S>(a, dag, has_a, norm, full, st, clov);
+    }
 }
 
 }  // namespace
@@ -268,37 +295,20 @@ int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov)
 {
-    const bool d = prec == HRD_F64;
-    switch (rep) {
-        case HRD_FUND:
-            return d ? dispatch_rupd<HRD_FUND, double>(a, st, clov) : dispatch_rupd<HRD_FUND, float>(a, st, clov);
-        case HRD_ADJ:
-            return d ? dispatch_rupd<HRD_ADJ, double>(a, st, clov) : dispatch_rupd<HRD_ADJ, float>(a, st, clov);
-        case HRD_FUND_SU2:
-            return d ? dispatch_rupd<HRD_FUND_SU2, double>(a, st, clov)
-                     : dispatch_rupd<HRD_FUND_SU2, float>(a, st, clov);
-        default:
-            return d ? dispatch_rupd<HRD_ADJ_SU2, double>(a, st, clov) : dispatch_rupd<HRD_ADJ_SU2, float>(a, st, clov);
+    switch (prec) {
+        case HRD_F64: return rupd_for<double>(rep, a, st, clov);
+        case HRD_F32: return rupd_for<float>(rep, a, st, clov);
+        default: return rupd_for<h16>(rep, a, st, clov);
     }
 }
 
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st, int clov)
 {
-    const bool d = prec == HRD_F64;
-    switch (rep) {
-        case HRD_FUND:
-            return d ? dispatch_hop_clov<HRD_FUND, double>(a, dag, has_a, norm, full, st, clov)
-                     : dispatch_hop_clov<HRD_FUND, float>(a, dag, has_a, norm, full, st, clov);
-        case HRD_ADJ:
-            return d ? dispatch_hop_clov<HRD_ADJ, double>(a, dag, has_a, norm, full, st, clov)
-                     : dispatch_hop_clov<HRD_ADJ, float>(a, dag, has_a, norm, full, st, clov);
-        case HRD_FUND_SU2:
-            return d ? dispatch_hop_clov<HRD_FUND_SU2, double>(a, dag, has_a, norm, full, st, clov)
-                     : dispatch_hop_clov<HRD_FUND_SU2, float>(a, dag, has_a, norm, full, st, clov);
-        default:
-            return d ? dispatch_hop_clov<HRD_ADJ_SU2, double>(a, dag, has_a, norm, full, st, clov)
-                     : dispatch_hop_clov<HRD_ADJ_SU2, float>(a, dag, has_a, norm, full, st, clov);
+    switch (prec) {
+        case HRD_F64: return hop_for<double>(rep, a, dag, has_a, norm, full, st, clov);
+        case HRD_F32: return hop_for<float>(rep, a, dag, has_a, norm, full, st, clov);
+        default: return hop_for<h16>(rep, a, dag, has_a, norm, full, st, clov);
     }
 }
 

@@ -47,6 +47,11 @@ hipError_t launch_convert_gauge(int rep, const Geom &g, const void *U64, void *U
 // nparity blocks of Vh sites, ncomp complex components per site
 hipError_t launch_convert_spinor(int Vh, int nparity, int ncomp, bool to_f32, const void *in, void *out,
                                  hipStream_t st);
+// F64 links -> F16 links
+hipError_t launch_convert_gauge_h16(int rep, const Geom &g, const void *U64, void *U16, hipStream_t st);
+// spinor storage conversion between any two precisions (same precision: copy)
+hipError_t launch_convert_spinor_prec(int rep, int Vh, int nparity, int prec_in, int prec_out, const void *in,
+                                      void *out, hipStream_t st);
 
 // ----- level-1 linear algebra (blas.hip) ------------------------------------
 // All reductions write kRedBlocks partials; finalize_* sums them in a fixed
@@ -93,6 +98,11 @@ hipError_t launch_cg_update_xp_mixed(int Vh, int ncomp, void *x64, void *p32, co
 hipError_t launch_cg_update_x_mixed(int Vh, int ncomp, void *x64, const void *p32, const double *sc, hipStream_t st);
 // p32 <- r32 + beta p32 with beta = rr / rr_old (after a reliable update).
 hipError_t launch_cg_update_p32(size_t n16, void *p32, const void *r32, const double *sc, hipStream_t st);
+// The same three updates with p in F16 storage (r stays F32, x F64).
+hipError_t launch_cg_update_xp_h16(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
+                                   hipStream_t st);
+hipError_t launch_cg_update_x_h16(int Vh, int ncomp, void *x64, const void *p16, const double *sc, hipStream_t st);
+hipError_t launch_cg_update_p16(int Vh, int ncomp, void *p16, const void *r32, const double *sc, hipStream_t st);
 // Reliable update: r64 = b - Ax64 ; r32 = f32(r64) ; partials of ||r64||^2.
 hipError_t launch_cg_residual_mixed(int Vh, int ncomp, const void *b, const void *Ax, void *r64, void *r32,
                                     double *partials, hipStream_t st);

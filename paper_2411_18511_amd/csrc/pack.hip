@@ -2,6 +2,8 @@
 // links and its chain rule, and precision conversions.  The paper precomputes
 // derived fields once per gauge update (Sec. 2.2); these kernels are that step
 // for the representation and the FP32 copy.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace hrd {
@@ -290,6 +292,50 @@ __global__ __launch_bounds__(kBlock) void convert_spinor_kernel(int Vh, int npar
     }
 }
 
+// F64 links -> F16 links (binary16 of the FP32 rounding of each entry); one
+// thread per (parity, direction, site).
+template <int REP>
+__global__ __launch_bounds__(kBlock) void convert_gauge_h16_kernel(Geom g, const void *U64, void *U16)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 8L * g.Vh) return;
+    const int pm = (int)(t / g.Vh);
+    const int idx = (int)(t - (long)pm * g.Vh);
+    const int p = pm >> 2, mu = pm & 3;
+    if constexpr (is_su2_row(REP)) {
+        RowIO<h16>::store(U16, g.Vh, p, mu, idx, RowIO<double>::load(U64, g.Vh, p, mu, idx));
+    } else {
+        LinkIO<REP, h16>::store(U16, g.Vh, p, mu, idx, LinkIO<REP, double>::load(U64, g.Vh, p, mu, idx));
+    }
+}
+
+// Spinor storage conversion, one thread per site of each parity block: the
+// input is read in its arithmetic type, rounded to the output's and stored
+// (F16 output computes its site scale in FP32); F16 -> F64 is exact.
+template <int NC, typename SI, typename SO>
+__global__ __launch_bounds__(kBlock) void convert_spinor_site_kernel(int Vh, int nparity, size_t in_blk,
+                                                                    size_t out_blk, const void *in, void *out)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)nparity * Vh) return;
+    const int blk = (int)(t / Vh);
+    const int site = (int)(t - (long)blk * Vh);
+    const char *src = reinterpret_cast<const char *>(in) + blk * in_blk;
+    char *dst = reinterpret_cast<char *>(out) + blk * out_blk;
+    using RO = typename Arith<SO>::type;
+    Cx<RO> co[NC];
+    if constexpr (std::is_same<SI, h16>::value && std::is_same<SO, double>::value) {
+        SpinorIO<h16>::load_exact<NC>(src, Vh, site, co);
+    } else {
+        using RI = typename Arith<SI>::type;
+        Cx<RI> ci[NC];
+        SpinorIO<SI>::template load<NC>(src, Vh, site, ci);
+#pragma unroll
+        for (int k = 0; k < NC; k++) co[k] = Cx<RO>{(RO)ci[k].re, (RO)ci[k].im};
+    }
+    SpinorIO<SO>::template store<NC>(dst, Vh, site, co);
+}
+
 inline dim3 grid_for(long n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 }  // namespace
@@ -360,6 +406,68 @@ hipError_t launch_convert_spinor(int Vh, int nparity, int ncomp, bool to_f32, co
 {
     const long n = (long)nparity * (ncomp / 2) * Vh;
     hipLaunchKernelGGL(convert_spinor_kernel, grid_for(n), dim3(kBlock), 0, st, Vh, nparity, ncomp, to_f32, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_gauge_h16(int rep, const Geom &g, const void *U64, void *U16, hipStream_t st)
+{
+    const dim3 grid = grid_for(8L * g.Vh);
+    switch (rep) {
+        case HRD_FUND: hipLaunchKernelGGL((convert_gauge_h16_kernel<HRD_FUND>), grid, dim3(kBlock), 0, st, g, U64, U16); break;
+        case HRD_ADJ: hipLaunchKernelGGL((convert_gauge_h16_kernel<HRD_ADJ>), grid, dim3(kBlock), 0, st, g, U64, U16); break;
+        case HRD_FUND_SU2:
+            hipLaunchKernelGGL((convert_gauge_h16_kernel<HRD_FUND_SU2>), grid, dim3(kBlock), 0, st, g, U64, U16);
+            break;
+        default:
+            hipLaunchKernelGGL((convert_gauge_h16_kernel<HRD_ADJ_SU2>), grid, dim3(kBlock), 0, st, g, U64, U16);
+            break;
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int NC, typename SI>
+void convert_from(int prec_out, int Vh, int nparity, size_t ib, size_t ob, const void *in, void *out, hipStream_t st)
+{
+    const dim3 grid = grid_for((long)nparity * Vh);
+    switch (prec_out) {
+        case HRD_F64:
+            hipLaunchKernelGGL((convert_spinor_site_kernel<NC, SI, double>), grid, dim3(kBlock), 0, st, Vh, nparity, ib,
+                               ob, in, out);
+            break;
+        case HRD_F32:
+            hipLaunchKernelGGL((convert_spinor_site_kernel<NC, SI, float>), grid, dim3(kBlock), 0, st, Vh, nparity, ib,
+                               ob, in, out);
+            break;
+        default:
+            hipLaunchKernelGGL((convert_spinor_site_kernel<NC, SI, h16>), grid, dim3(kBlock), 0, st, Vh, nparity, ib,
+                               ob, in, out);
+            break;
+    }
+}
+
+template <int NC>
+void convert_nc(int prec_in, int prec_out, int Vh, int nparity, size_t ib, size_t ob, const void *in, void *out,
+                hipStream_t st)
+{
+    switch (prec_in) {
+        case HRD_F64: convert_from<NC, double>(prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case HRD_F32: convert_from<NC, float>(prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        default: convert_from<NC, h16>(prec_out, Vh, nparity, ib, ob, in, out, st); break;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_convert_spinor_prec(int rep, int Vh, int nparity, int prec_in, int prec_out, const void *in,
+                                      void *out, hipStream_t st)
+{
+    const size_t ib = (size_t)Vh * spinor_site_bytes(rep, prec_in);
+    const size_t ob = (size_t)Vh * spinor_site_bytes(rep, prec_out);
+    if (prec_in == prec_out) return launch_copy(ib * nparity, in, out, st);
+    if (ncolour(rep) == 2) convert_nc<8>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st);
+    else convert_nc<12>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st);
     return hipGetLastError();
 }
 

@@ -28,22 +28,23 @@ _lib = ctypes.CDLL(LIBPATH)
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
 FUND, ADJ, FUND_SU2, ADJ_SU2 = 0, 1, 2, 3
-F64, F32 = 0, 1
+F64, F32, F16 = 0, 1, 2
 FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
 SITES_ALL, SITES_EVEN, SITES_ODD = 0, 1, 2
-CG_F64, CG_MIXED = 0, 1
+CG_F64, CG_MIXED, CG_MIXED16 = 0, 1, 2
 
 _STATUS_NAMES = {0: "HRD_OK", 1: "HRD_EINVAL", 2: "HRD_ESHAPE", 3: "HRD_EALIAS", 4: "HRD_EHIP",
                  5: "HRD_ENOCONV", 6: "HRD_EBREAKDOWN", 7: "HRD_ESIZE"}
 _REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, "fund_su2": FUND_SU2,
          "adj_su2": ADJ_SU2, FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2}
-_PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, F64: F64, F32: F32,
-          torch.float64: F64, torch.float32: F32}
+_PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "f16": F16, "fp16": F16, F64: F64, F32: F32,
+          F16: F16, torch.float64: F64, torch.float32: F32}
 _PARITIES = {"full": FULL, "eo": EO, "hop_eo": HOP_EO, "hop_oe": HOP_OE,
              FULL: FULL, EO: EO, HOP_EO: HOP_EO, HOP_OE: HOP_OE}
 _SITES = {"all": SITES_ALL, "even": SITES_EVEN, "odd": SITES_ODD,
           SITES_ALL: SITES_ALL, SITES_EVEN: SITES_EVEN, SITES_ODD: SITES_ODD}
-_MODES = {"f64": CG_F64, "fp64": CG_F64, "mixed": CG_MIXED, CG_F64: CG_F64, CG_MIXED: CG_MIXED}
+_MODES = {"f64": CG_F64, "fp64": CG_F64, "mixed": CG_MIXED, "mixed16": CG_MIXED16, CG_F64: CG_F64,
+          CG_MIXED: CG_MIXED, CG_MIXED16: CG_MIXED16}
 
 
 class HrdError(RuntimeError):
@@ -105,6 +106,8 @@ _sig("hrd_convert_gauge", _I, _LP, _I, _P, _P, _P)
 _sig("hrd_pack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
 _sig("hrd_unpack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
 _sig("hrd_convert_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
+_sig("hrd_convert_spinor_prec", _I, _LP, _I, _I, _I, _I, _P, _P, _P)
+_sig("hrd_convert_gauge_prec", _I, _LP, _I, _I, _P, _P, _P)
 _sig("hrd_dirac_workspace_bytes", _S, _LP, _I, _I, _I)
 _sig("hrd_dirac_apply", _I, _LP, _I, _I, _P, _P, _P, _D, _I, _I, _P, _P)
 _sig("hrd_blas_workspace_bytes", _S)
@@ -284,6 +287,24 @@ def convert_spinor(psi, dims, rep, nparity, to_f32):
     return out
 
 
+def convert_spinor_prec(psi, dims, rep, nparity, prec_in, prec_out):
+    """Packed spinor in prec_in -> new packed spinor in prec_out (F64, F32, F16)."""
+    rep, pi, po = _REPS[rep], _PRECS[prec_in], _PRECS[prec_out]
+    _need(psi, spinor_bytes(dims, rep, pi, nparity), "psi")
+    out = _empty(spinor_bytes(dims, rep, po, nparity), psi.device)
+    _check(_lib.hrd_convert_spinor_prec(ctypes.byref(lattice(dims)), rep, int(nparity), pi, po, _ptr(psi), _ptr(out),
+                                        _stream()))
+    return out
+
+
+def convert_gauge_prec(U64, dims, rep, prec_out):
+    """Packed FP64 gauge field -> packed F32 or F16 copy."""
+    rep, po = _REPS[rep], _PRECS[prec_out]
+    out = _empty(gauge_bytes(dims, rep, po), U64.device)
+    _check(_lib.hrd_convert_gauge_prec(ctypes.byref(lattice(dims)), rep, po, _ptr(U64), _ptr(out), _stream()))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # operator
 # ---------------------------------------------------------------------------
@@ -395,7 +416,8 @@ def cg_workspace_bytes(dims, rep, mode):
 
 def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=10000, delta=0.1, work=None,
              allow_noconv=False):
-    """Solve (D^+ D^) x = b on even sites; returns (x, info dict)."""
+    """Solve (D^+ D^) x = b on even sites; returns (x, info dict).  U32 is the
+    reduced-precision gauge copy: FP32 for mode 'mixed', F16 for 'mixed16'."""
     rep, mode = _REPS[rep], _MODES[mode]
     nb = spinor_bytes(dims, rep, F64, 1)
     _need(b, nb, "b")
@@ -467,9 +489,11 @@ def unpack_clover(C64, dims, rep):
     return out
 
 
-def dirac_apply_clover(U, clov, psi, rep, parity, dims, dagger=False, out=None, work=None):
-    """out = D_sw psi ('full') or D^_sw psi_e ('eo'); precision is that of clov."""
-    rep, parity, prec = _REPS[rep], _PARITIES[parity], clov.prec
+def dirac_apply_clover(U, clov, psi, rep, parity, dims, dagger=False, out=None, work=None, prec=None):
+    """out = D_sw psi ('full') or D^_sw psi_e ('eo'); the precision is that of
+    clov unless prec = 'f16' is given (F16 fields with FP32 clover fields)."""
+    rep, parity = _REPS[rep], _PARITIES[parity]
+    prec = clov.prec if prec is None else _PRECS[prec]
     np_ = 2 if parity == FULL else 1
     nbytes = spinor_bytes(dims, rep, prec, np_)
     _need(psi, nbytes, "psi")
@@ -488,8 +512,9 @@ def dirac_apply_clover(U, clov, psi, rep, parity, dims, dagger=False, out=None, 
 class CloverOp:
     """Prepared ``dirac_apply_clover`` (one foreign call per application)."""
 
-    def __init__(self, U, clov, dims, rep, parity, dagger=False):
-        self.rep, self.prec, self.parity = _REPS[rep], clov.prec, _PARITIES[parity]
+    def __init__(self, U, clov, dims, rep, parity, dagger=False, prec=None):
+        self.rep, self.parity = _REPS[rep], _PARITIES[parity]
+        self.prec = clov.prec if prec is None else _PRECS[prec]
         _need(U, gauge_bytes(dims, self.rep, self.prec), "U")
         self._keep = (U, clov)
         self._lat = lattice(dims)
