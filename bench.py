@@ -18,7 +18,7 @@ One step = one pass over every stage of the hot path:
      library provides it);
   6. the clover-improved operator (Sec. 2.2), Sheikholeslami-Wohlert and
      exponentiated, c_sw = 1: site-matrix build, even/odd D^_sw in FP64 and
-     FP32, and CG on D^_sw^+ D^_sw in FP64 and mixed precision.
+     FP32, and CG on D^_sw^+ D^_sw in FP64 and mixed precision (FP32 and F16).
 
 Prints one JSON line.  `value` is the FP64 Dslash (hopping block) bandwidth
 on algorithmic bytes: each link, each source spinor and each output spinor
@@ -336,7 +336,11 @@ def main():
                     r[f"cg_clover_{kind}_mixed_ms"], (_, icm) = timed_once(
                         lambda: hrd.cg_solve_clover(U64, c64, src_e, tol, dims, fmt, mode="mixed", U32=U32,
                                                     clov32=c32))
+                    r[f"cg_clover_{kind}_mixed16_ms"], (_, ich) = timed_once(
+                        lambda: hrd.cg_solve_clover(U64, c64, src_e, tol, dims, fmt, mode="mixed16", U32=U16,
+                                                    clov32=c32))
                     r[f"cg_clover_{kind}_f64"], r[f"cg_clover_{kind}_mixed"] = ic64, icm
+                    r[f"cg_clover_{kind}_mixed16"] = ich
                     del c64, c32, cd64, cd32
             del U64, U32, U16, x64, xm, xh, d
         return r
@@ -407,7 +411,9 @@ def main():
                                   "over_wilson_dhat": ms / avg(f"dhat_{prec}_fund")}
         d_["cg_f64"] = {"ms": avg(f"cg_clover_{kind}_f64_ms"), **per[-1][f"cg_clover_{kind}_f64"]}
         d_["cg_mixed"] = {"ms": avg(f"cg_clover_{kind}_mixed_ms"), **per[-1][f"cg_clover_{kind}_mixed"]}
+        d_["cg_mixed16"] = {"ms": avg(f"cg_clover_{kind}_mixed16_ms"), **per[-1][f"cg_clover_{kind}_mixed16"]}
         d_["mixed_over_f64_time"] = d_["cg_mixed"]["ms"] / d_["cg_f64"]["ms"]
+        d_["mixed16_over_f64_time"] = d_["cg_mixed16"]["ms"] / d_["cg_f64"]["ms"]
         clover[kind] = d_
     hop = dslash["hop_f64_fund"]
     hop_gbs = hop["alg_GBs"]
