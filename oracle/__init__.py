@@ -427,3 +427,76 @@ def round_links16(U):
     if np.iscomplexobj(U):
         return r(U.real) + 1j * r(U.imag)
     return r(U)
+
+
+# ---------------------------------------------------------------------------
+# SU(N) and its two-index representations (the paper's Sec. 1: HiRep runs
+# SU(N) gauge theories with fermions in the fundamental and higher
+# representations).  The representation of a link is the matrix of the
+# group action on an orthonormal basis of the representation space; the
+# operator's spectrum does not depend on which basis is taken.
+# ---------------------------------------------------------------------------
+
+def su_generators(nc):
+    """Hermitian traceless generators T_a of su(nc), tr(T_a T_b) = delta_ab / 2:
+    the symmetric, antisymmetric and diagonal generalised Gell-Mann matrices, halved."""
+    T = []
+    for j in range(nc):
+        for k in range(j + 1, nc):
+            m = np.zeros((nc, nc), np.complex128)
+            m[j, k] = m[k, j] = 0.5
+            T.append(m)
+            m = np.zeros((nc, nc), np.complex128)
+            m[j, k] = -0.5j
+            m[k, j] = 0.5j
+            T.append(m)
+    for l in range(1, nc):
+        m = np.zeros((nc, nc), np.complex128)
+        for j in range(l):
+            m[j, j] = 1.0
+        m[l, l] = -float(l)
+        T.append(m / np.sqrt(2.0 * l * (l + 1)))
+    return np.array(T)
+
+
+def two_index_basis(nc, kind):
+    """Orthonormal basis of symmetric ("sym") or antisymmetric ("asym") nc x nc
+    matrices (Frobenius inner product), in the order (i, j), i <= j (sym) or
+    i < j (asym), row-major."""
+    E = []
+    for i in range(nc):
+        for j in range(i, nc):
+            if i == j and kind == "asym":
+                continue
+            m = np.zeros((nc, nc), np.complex128)
+            if i == j:
+                m[i, i] = 1.0
+            else:
+                m[i, j] = 1.0 / np.sqrt(2.0)
+                m[j, i] = (1.0 if kind == "sym" else -1.0) / np.sqrt(2.0)
+            E.append(m)
+    return np.array(E)
+
+
+def rep_dim(nc, rep):
+    return {"fund": nc, "adj": nc * nc - 1, "sym": nc * (nc + 1) // 2, "asym": nc * (nc - 1) // 2}[rep]
+
+
+def represent(U, rep):
+    """Links of the representation rep of SU(nc) from fundamental links U [..., nc, nc]:
+      fund : U;
+      adj  : R_ab = 2 tr(T_a U T_b U^+), real orthogonal (nc^2 - 1);
+      sym  : R_kl = tr(E_k^+ U E_l U^T) over the symmetric basis (nc (nc + 1) / 2);
+      asym : the same over the antisymmetric basis (nc (nc - 1) / 2);
+    the two-index maps are the action M -> U M U^T of U (x) U on matrices."""
+    U = _cplx(U)
+    nc = U.shape[-1]
+    if rep == "fund":
+        return U.copy()
+    if rep == "adj":
+        T = su_generators(nc)
+        Ud = np.conj(np.swapaxes(U, -1, -2))
+        R = 2.0 * np.einsum("aij,...jk,bkl,...li->...ab", T, U, T, Ud)
+        return R.real.copy()
+    E = two_index_basis(nc, rep)
+    return np.einsum("kji,...jm,lmn,...in->...kl", np.conj(E), U, E, U)

@@ -35,7 +35,7 @@
 
 typedef double complex cplx;
 
-#define MAXN 3
+#define MAXN 16
 
 /* Coordinates of lexicographic site index s. */
 static void coords(const int *d, long s, int x[4])

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs: SU(2) gauge fields and Gaussian spinor fields.
+"""Seeded synthetic inputs: SU(2) and SU(N) gauge fields, Gaussian spinor fields.
 
 This module holds no part of the Dirac operator, the solver or the force; it
 only draws random fields, in the natural layout
@@ -18,6 +18,11 @@ Table 1); bandwidth does not depend on field content, so these stand in:
   directions pulled toward the identity.  For independent links the mean
   plaquette is E[a0]^4, so eps is chosen by bisection to make E[a0]^4 equal
   the requested plaquette (0.6 by default).
+* SU(N) links (N >= 2): Haar-random unitary matrices from the QR
+  factorisation of a complex Gaussian matrix with the phases of R's diagonal
+  divided out (Mezzadri's method), then divided by an N-th root of the
+  determinant; "smeared" SU(N) links are exp(i eps H) with H a Gaussian
+  traceless Hermitian matrix (near the identity).
 * Spinors: real and imaginary parts i.i.d. N(0, 1/2).
 """
 import numpy as np
@@ -87,6 +92,42 @@ def gauge_field(dims, seed, kind="haar", plaquette=0.6):
     raise ValueError(f"unknown gauge kind {kind!r}")
 
 
+def haar_sun(rng, shape, nc):
+    """Haar-random SU(nc) matrices [..., nc, nc]."""
+    shape = tuple(shape)
+    z = (rng.standard_normal(shape + (nc, nc)) + 1j * rng.standard_normal(shape + (nc, nc))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r, axis1=-2, axis2=-1)
+    q = q * (d / np.abs(d))[..., None, :]
+    det = np.linalg.det(q)
+    return q / (det ** (1.0 / nc))[..., None, None]
+
+
+def smeared_sun(rng, shape, nc, eps=0.35):
+    """SU(nc) matrices exp(i eps H), H Gaussian, Hermitian and traceless."""
+    shape = tuple(shape)
+    z = rng.standard_normal(shape + (nc, nc)) + 1j * rng.standard_normal(shape + (nc, nc))
+    h = (z + np.conj(np.swapaxes(z, -1, -2))) / 2
+    h = h - np.trace(h, axis1=-2, axis2=-1)[..., None, None] * np.eye(nc) / nc
+    w, v = np.linalg.eigh(h)
+    return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * eps * w), np.conj(v))
+
+
+def gauge_field_sun(dims, seed, nc, kind="haar"):
+    """Fundamental SU(nc) gauge field [4, T, L1, L2, L3, nc, nc] (complex128)."""
+    if nc == 2:
+        return gauge_field(dims, seed, kind=kind)
+    rng = rng_for(seed)
+    shape = (4,) + tuple(int(d) for d in dims)
+    if kind == "haar":
+        return haar_sun(rng, shape, nc)
+    if kind == "smeared":
+        return smeared_sun(rng, shape, nc)
+    if kind == "unit":
+        return np.broadcast_to(np.eye(nc, dtype=np.complex128), shape + (nc, nc)).copy()
+    raise ValueError(f"unknown gauge kind {kind!r}")
+
+
 def gaussian_spinor(dims, ncolour, seed, nrhs=None):
     """Gaussian spinor field [T, L1, L2, L3, 4, N] (or [nrhs, ...]), complex128."""
     rng = rng_for(seed)
@@ -98,6 +139,8 @@ def gaussian_spinor(dims, ncolour, seed, nrhs=None):
     return (re + 1j * im) * np.sqrt(0.5)
 
 
-def gauge_transform(rng, dims):
-    """Random site-local SU(2) matrices g(x), shape [T, L1, L2, L3, 2, 2]."""
-    return haar_su2(rng, tuple(int(d) for d in dims))
+def gauge_transform(rng, dims, nc=2):
+    """Random site-local SU(nc) matrices g(x), shape [T, L1, L2, L3, nc, nc]."""
+    if nc == 2:
+        return haar_su2(rng, tuple(int(d) for d in dims))
+    return haar_sun(rng, tuple(int(d) for d in dims), nc)
