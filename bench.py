@@ -194,6 +194,85 @@ def mixed_volume_cg(torch, hrd, inputs, dev, nrhs=12, tol=1e-10):
             "iters_batched_max": max(i["iters"] for i in infos), "iters_single_max": max(seq_iters)}
 
 
+SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx6": 36 * 16, "real8": 64 * 8}  # FP64, unpadded
+
+
+def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10, m0=-0.3):
+    """SU(3) with fermions in the fundamental (CPLX3), 2-index symmetric (CPLX6)
+    and adjoint (REAL8) representations: representation build, hopping block
+    in FP64 / FP32 / F16 and even/odd D^ in FP32 (algorithmic bytes on
+    unpadded links), and mixed / MIXED16 CG to 1e-10 for the fundamental."""
+    V = int(np.prod(dims))
+    Uf = inputs.gauge_field_sun(dims, 7, 3, kind="product")
+    Uf_dev = torch.from_numpy(Uf.reshape(4, V, 3, 3)).to(dev)
+    del Uf
+    Uf64 = hrd.pack_gauge(Uf_dev, dims, "cplx3", "f64")
+    del Uf_dev
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    out = {"dims": list(dims), "group": "SU(3)", "links": "products of embedded Haar SU(2) elements"}
+    for rep in ("fund", "sym", "adj"):
+        fmt = hrd.sun_rep_format(3, rep)
+        name = {hrd.CPLX3: "cplx3", hrd.CPLX6: "cplx6", hrd.REAL8: "real8"}[fmt]
+        n = hrd.ncolour(fmt)
+        a, b = ev(), ev()
+        a.record()
+        U64 = hrd.represent_sun(Uf64, dims, 3, rep)
+        b.record()
+        b.synchronize()
+        r = {"format": name, "N_R": n, "represent_ms": a.elapsed_time(b)}
+        psi = torch.from_numpy(inputs.gaussian_spinor(dims, n, 8).reshape(V, 4, n)).to(dev)
+        src_o = hrd.pack_spinor(psi, dims, fmt, "f64", "odd")
+        src_e = hrd.pack_spinor(psi, dims, fmt, "f64", "even")
+        del psi
+        for prec in ("f64", "f32", "f16"):
+            Ug = U64 if prec == "f64" else hrd.convert_gauge_prec(U64, dims, fmt, prec)
+            so = hrd.convert_spinor_prec(src_o, dims, fmt, 1, "f64", prec)
+            se = hrd.convert_spinor_prec(src_e, dims, fmt, 1, "f64", prec)
+            dst = torch.empty_like(se)
+            hop = hrd.DiracOp(Ug, dims, fmt, prec, m0, "hop_eo")
+            hop(so, dst)
+            a.record()
+            for _ in range(reps):
+                hop(so, dst)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b) / reps
+            L = SUN_LINK_BYTES[name] // {"f64": 1, "f32": 2, "f16": 4}[prec]
+            S = {"f64": 64 * n, "f32": 32 * n, "f16": 16 * n + 4}[prec]
+            alg = (V // 2) * (8 * L + 2 * S)
+            r[f"hop_{prec}"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
+                                "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if prec == "f32":
+                dh = hrd.DiracOp(Ug, dims, fmt, prec, m0, "eo")
+                dh(se, dst)
+                a.record()
+                for _ in range(reps // 2):
+                    dh(se, dst)
+                b.record()
+                b.synchronize()
+                ms = a.elapsed_time(b) / (reps // 2)
+                alg = V * 8 * L + (V // 2) * 5 * S
+                r["dhat_f32"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
+                                 "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if rep == "fund" and prec != "f64":
+                mode = "mixed" if prec == "f32" else "mixed16"
+                a.record()
+                _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode=mode, U32=Ug)
+                b.record()
+                b.synchronize()
+                r[f"cg_{mode}"] = {"ms": a.elapsed_time(b), **info}
+            del Ug, so, se, dst
+        if rep == "fund":
+            a.record()
+            _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="f64")
+            b.record()
+            b.synchronize()
+            r["cg_f64"] = {"ms": a.elapsed_time(b), **info}
+        out[rep] = r
+        del U64, src_o, src_e
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +283,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-config4", action="store_true", help="skip the mixed-volume batched CG comparison")
+    ap.add_argument("--no-sun", action="store_true", help="skip the SU(3) representations stage")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the lattice is not sharded "
@@ -458,6 +538,9 @@ def main():
                                    "single_dhat_f32_ms": avg(f"dhat_f32_{fmt}")}
     if batched_ok and not args.no_config4:
         out["batched_cg_mixed_volumes"] = mixed_volume_cg(torch, hrd, inputs, dev)
+    if not args.no_sun:
+        print("[bench] SU(3) representations stage", file=sys.stderr, flush=True)
+        out["sun"] = sun_stage(torch, hrd, inputs, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(U_np, psi_np, V)
     print(json.dumps(out), flush=True)

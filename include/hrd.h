@@ -67,6 +67,13 @@
  *     link FUND_SU2, ADJ_SU2 F16: 1 plane of 4 binary16 (U00, U01).
  *     F16 links carry no scale (entries are bounded by 1); each entry is the
  *     binary16 of its float32 rounding.
+ *     link CPLXn (n x n complex, entry e = n i + j): F64 n^2 planes of
+ *                    complex128; F32 ceil(n^2/2) planes of 2 x complex64
+ *                    (entries 2q, 2q+1); F16 ceil(n^2/4) planes of 4 complex
+ *                    as 8 binary16 (entries 4q .. 4q+3).  Slots past the last
+ *                    entry are padding (written as zero).
+ *     link REAL8 (8 x 8 real, entry e = 8 i + j): F64 32 planes of 2 float64,
+ *                    F32 16 planes of 4 float32, F16 8 planes of 8 binary16.
  *   A full-lattice spinor is [parity][planes][Vh], even block first.  A
  *   gauge field is [parity][mu][planes][Vh]: block (p, mu) holds the links
  *   U_mu(x) of the sites x of parity p.
@@ -74,7 +81,8 @@
  * NATURAL LAYOUTS (device memory; used only by the pack/unpack calls)
  *   spinor : complex128 [V][4][N]          (site lex, spin, colour)
  *   gauge  : complex128 [4][V][2][2] FUND, FUND_SU2 and ADJ_SU2 (the
- *            fundamental links), float64 [4][V][3][3] ADJ
+ *            fundamental links), float64 [4][V][3][3] ADJ, complex128
+ *            [4][V][n][n] CPLXn, float64 [4][V][8][8] REAL8
  *
  * OWNERSHIP AND ERRORS
  *   Every field pointer is a device pointer owned by the caller; the library
@@ -116,7 +124,26 @@ typedef enum {
    from that row inside the kernels (the quaternion form of R).  This halves
    (FUND) or cuts by 5/9 (ADJ) the link bytes the operator reads; it assumes
    the links are exactly of SU(2) form. */
-typedef enum { HRD_FUND = 0, HRD_ADJ = 1, HRD_FUND_SU2 = 2, HRD_ADJ_SU2 = 3 } hrd_rep;
+typedef enum {
+    HRD_FUND = 0,
+    HRD_ADJ = 1,
+    HRD_FUND_SU2 = 2,
+    HRD_ADJ_SU2 = 3,
+    /* SU(N > 2) (Sec. 1: SU(N) with fermions in higher representations):
+       links of the fermion representation stored as dense matrices.  The
+       representation fixes only the colour count N_R and whether links are
+       complex or real:
+         HRD_CPLX3 : complex 3x3 (SU(3) fundamental, SU(3) 2-index antisymmetric)
+         HRD_CPLX4 : complex 4x4 (SU(4) fundamental)
+         HRD_CPLX6 : complex 6x6 (SU(3) 2-index symmetric, SU(4) 2-index
+                     antisymmetric)
+         HRD_REAL8 : real 8x8    (SU(3) adjoint)
+       hrd_represent_sun builds them from fundamental SU(N) links. */
+    HRD_CPLX3 = 4,
+    HRD_CPLX4 = 5,
+    HRD_CPLX6 = 6,
+    HRD_REAL8 = 7
+} hrd_rep;
 /* Storage precision of a field.  HRD_F16 is the 16-bit storage of the mixed
    solver's inner iterations (binary16 values, FP32 arithmetic; spinors carry
    a per-site FP32 scale, see PACKED LAYOUTS).  Calls that accept HRD_F16 say
@@ -189,6 +216,28 @@ hrd_status hrd_unpack_gauge(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
    written in the packed ADJ layout of precision prec_out. */
 hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj,
                          hrd_prec prec_out, void *stream);
+
+/* Representations of SU(N > 2) (Sec. 1).  kind selects the representation;
+   hrd_sun_rep_format returns the link format of (nc, kind), or -1 when none
+   exists:  SU(3): FUND -> HRD_CPLX3, ADJ -> HRD_REAL8, SYM -> HRD_CPLX6,
+   ASYM -> HRD_CPLX3;  SU(4): FUND -> HRD_CPLX4, ASYM -> HRD_CPLX6.
+   Bases: ADJ R_ab = 2 Re tr(T_a U T_b U^+) with T_a the generalised Gell-Mann
+   matrices halved, ordered pairwise (j < k: symmetric then antisymmetric)
+   then diagonal diag(1, .., 1, -l, 0, ..) / sqrt(2 l (l + 1)); SYM / ASYM
+   the action U M U^T on symmetric / antisymmetric matrices in the
+   orthonormal basis e_i e_i^T (SYM only), (e_i e_j^T +- e_j e_i^T)/sqrt(2),
+   pairs (i, j) row-major.  The operator's spectrum does not depend on the
+   basis. */
+typedef enum { HRD_SUN_FUND = 0, HRD_SUN_ADJ = 1, HRD_SUN_SYM = 2, HRD_SUN_ASYM = 3 } hrd_sun_rep;
+
+int hrd_sun_rep_format(int nc, int kind);
+
+/* U_rep (packed FP64, format hrd_sun_rep_format(nc, kind)) = the
+   representation of the packed FP64 fundamental SU(nc) field U_fund (format
+   HRD_CPLX3 for nc = 3, HRD_CPLX4 for nc = 4).  The links are taken as given
+   (no reunitarisation).  Asynchronous. */
+hrd_status hrd_represent_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind, const void *U_fund,
+                             void *U_rep, void *stream);
 
 /* Chain rule through the adjoint map: given the packed FP64 fundamental field
    U_fund and a packed FP64 ADJ field g = dL/dR (real), writes the packed FP64

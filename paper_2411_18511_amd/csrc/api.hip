@@ -47,6 +47,12 @@ hrd_status check_lattice(const hrd_lattice *lat)
     return HRD_OK;
 }
 
+hrd_status check_su2_format(hrd_rep rep, const char *what)
+{
+    if (is_dense(rep)) return fail(HRD_EINVAL, "%s supports the SU(2) link formats only (rep %d)", what, (int)rep);
+    return HRD_OK;
+}
+
 hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec)
 {
     if (prec == HRD_F16) return check_rep_prec(rep, HRD_F64);
@@ -55,7 +61,7 @@ hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec)
 
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
 {
-    if (rep < HRD_FUND || rep > HRD_ADJ_SU2) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
+    if (rep < HRD_FUND || rep > HRD_REAL8) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
     if (prec != HRD_F64 && prec != HRD_F32) return fail(HRD_EINVAL, "invalid precision %d", (int)prec);
     return HRD_OK;
 }
@@ -295,6 +301,39 @@ hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj
     return check_hip(launch_represent(prec_out, g, U_fund, U_adj, (hipStream_t)stream), "represent launch");
 }
 
+int hrd_sun_rep_format(int nc, int kind)
+{
+    if (nc == 3) {
+        switch (kind) {
+            case HRD_SUN_FUND: return HRD_CPLX3;
+            case HRD_SUN_ADJ: return HRD_REAL8;
+            case HRD_SUN_SYM: return HRD_CPLX6;
+            case HRD_SUN_ASYM: return HRD_CPLX3;
+            default: return -1;
+        }
+    }
+    if (nc == 4) {
+        if (kind == HRD_SUN_FUND) return HRD_CPLX4;
+        if (kind == HRD_SUN_ASYM) return HRD_CPLX6;
+    }
+    return -1;
+}
+
+hrd_status hrd_represent_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind, const void *U_fund, void *U_rep,
+                             void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    const int out = hrd_sun_rep_format(nc, kind);
+    if (out < 0) return fail(HRD_EINVAL, "no link format for SU(%d) representation %d", nc, (int)kind);
+    if (!U_fund || !U_rep) return fail(HRD_EINVAL, "NULL field pointer");
+    const int in = nc == 3 ? HRD_CPLX3 : HRD_CPLX4;
+    if (overlap(U_fund, gauge_bytes(lat, in, HRD_F64), U_rep, gauge_bytes(lat, out, HRD_F64)))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_represent_sun(nc, (int)kind, g, U_fund, U_rep, (hipStream_t)stream),
+                     "represent_sun launch");
+}
+
 hrd_status hrd_represent_backward(const hrd_lattice *lat, const void *U_fund, const void *g_adj, void *G_fund,
                                   void *stream)
 {
@@ -431,7 +470,7 @@ hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 
 size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK || is_dense(rep)) return 0;
     return clover_bytes(lat, rep, prec);
 }
 
@@ -439,6 +478,7 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind
                             double m0, void *M64, void *Minv64, void *stream)
 {
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_clover_build"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (kind != HRD_CLOVER_SW && kind != HRD_CLOVER_EXP) return fail(HRD_EINVAL, "invalid clover kind %d", (int)kind);
     if (!U64 || !M64 || !Minv64) return fail(HRD_EINVAL, "NULL field pointer");
@@ -457,6 +497,7 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind
 hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C32, void *stream)
 {
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_convert_clover"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!C64 || !C32) return fail(HRD_EINVAL, "NULL field pointer");
     if (overlap(C64, clover_bytes(lat, rep, HRD_F64), C32, clover_bytes(lat, rep, HRD_F32)))
@@ -468,6 +509,7 @@ hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C
 hrd_status hrd_unpack_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C_nat, void *stream)
 {
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_unpack_clover"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!C64 || !C_nat) return fail(HRD_EINVAL, "NULL field pointer");
     const size_t cb = clover_bytes(lat, rep, HRD_F64);
@@ -481,6 +523,7 @@ hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec 
                                   void *work, void *stream)
 {
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_dirac_apply_clover"));
     HRD_TRY(check_rep_prec_any(rep, prec));
     if (parity != HRD_FULL && parity != HRD_EO)
         return fail(HRD_EINVAL, "clover operator supports HRD_FULL and HRD_EO (hop blocks are those of hrd_dirac_apply)");
@@ -612,6 +655,7 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     if (mode != HRD_CG_F64 && !U32)
         return finish(fail(HRD_EINVAL, "mixed CG needs the reduced-precision gauge field (FP32 or F16)"));
     if (!cl64 && (!std::isfinite(m0) || 4.0 + m0 == 0.0)) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
+    if (cl64 && is_dense(rep)) return finish(check_su2_format(rep, "hrd_cg_solve_clover"));
     if (cl64 && (!cl64->M || !cl64->Minv)) return finish(fail(HRD_EINVAL, "NULL FP64 clover field"));
     if (cl64 && mode != HRD_CG_F64 && (!cl32 || !cl32->M || !cl32->Minv))
         return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 clover fields"));
@@ -805,6 +849,7 @@ hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 {
     (void)U;
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_dirac_force"));
     HRD_TRY(check_rep_prec(rep, prec));
     if (prec != HRD_F64) return fail(HRD_EINVAL, "the force is computed in FP64 only");
     if (!X || !Y || !F) return fail(HRD_EINVAL, "NULL field pointer");
@@ -817,7 +862,7 @@ hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 
 size_t hrd_action_force_workspace_bytes(const hrd_lattice *lat, hrd_rep rep)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK || is_dense(rep)) return 0;
     return 2 * spinor_bytes(lat, rep, HRD_F64, 2) + 256;
 }
 
@@ -825,6 +870,7 @@ hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U, 
                             double scale, void *work, size_t work_bytes, void *stream)
 {
     HRD_TRY(check_lattice(lat));
+    HRD_TRY(check_su2_format(rep, "hrd_action_force"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!U || !xi || !F || !work) return fail(HRD_EINVAL, "NULL pointer");
     if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return fail(HRD_EINVAL, "invalid m0 %g", m0);

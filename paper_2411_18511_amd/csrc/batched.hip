@@ -358,6 +358,7 @@ hrd_status check_problems(const hrd_problem *probs, int nprob, bool need_u64)
         const hrd_problem &p = probs[i];
         HRD_TRY(check_lattice(&p.lat));
         HRD_TRY(check_rep_prec(p.rep, HRD_F32));
+        if (is_dense(p.rep)) return fail(HRD_EINVAL, "problem %d: batched launches take the SU(2) link formats", i);
         if (p.nrhs < 1 || p.nrhs > kMaxRhs) return fail(HRD_EINVAL, "problem %d: nrhs must be in 1..%d", i, kMaxRhs);
         if (!p.U32 || !p.src || !p.dst) return fail(HRD_EINVAL, "problem %d: NULL pointer", i);
         if (need_u64 && !p.U64) return fail(HRD_EINVAL, "problem %d: the batched CG needs U64", i);

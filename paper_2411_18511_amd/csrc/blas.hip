@@ -476,8 +476,13 @@ hipError_t launch_h16_update(int Vh, int ncomp, void *x64, void *p16, const void
                              hipStream_t st)
 {
     const dim3 grid((unsigned)((Vh + kBlock - 1) / kBlock));
-    if (ncomp == 8) hipLaunchKernelGGL((cg_update_h16_kernel<8, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc);
-    else hipLaunchKernelGGL((cg_update_h16_kernel<12, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc);
+    switch (ncomp) {
+        case 8: hipLaunchKernelGGL((cg_update_h16_kernel<8, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+        case 12: hipLaunchKernelGGL((cg_update_h16_kernel<12, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+        case 16: hipLaunchKernelGGL((cg_update_h16_kernel<16, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+        case 24: hipLaunchKernelGGL((cg_update_h16_kernel<24, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+        default: hipLaunchKernelGGL((cg_update_h16_kernel<32, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+    }
     return hipGetLastError();
 }
 

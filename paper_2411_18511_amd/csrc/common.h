@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 #include "hrd.h"
 
@@ -416,17 +417,38 @@ struct AdjLink {
 __host__ __device__ constexpr bool is_su2_row(int rep) { return rep == HRD_FUND_SU2 || rep == HRD_ADJ_SU2; }
 
 // Number of colours of the fermion in a representation.
-__host__ __device__ constexpr int ncolour(int rep) { return (rep == HRD_FUND || rep == HRD_FUND_SU2) ? 2 : 3; }
+__host__ __device__ constexpr int ncolour(int rep)
+{
+    return (rep == HRD_FUND || rep == HRD_FUND_SU2) ? 2
+           : (rep == HRD_ADJ || rep == HRD_ADJ_SU2 || rep == HRD_CPLX3) ? 3
+           : rep == HRD_CPLX4 ? 4
+           : rep == HRD_CPLX6 ? 6
+           : 8;
+}
+
+// Dense link formats of SU(N > 2) representations.
+__host__ __device__ constexpr bool is_dense(int rep) { return rep >= HRD_CPLX3; }
+__host__ __device__ constexpr bool is_real_dense(int rep) { return rep == HRD_REAL8; }
 
 // Representation whose (uncompressed) layout a derivative with respect to the
-// links uses: FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2.
-__host__ __device__ constexpr int base_rep(int rep) { return ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ; }
+// links uses: FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2, the format
+// itself for the dense formats.
+__host__ __device__ constexpr int base_rep(int rep)
+{
+    return is_dense(rep) ? rep : ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ;
+}
 
-// Bytes per link: real entries (8 FUND, 9 ADJ, 4 for a first row) times the
-// storage width (8 F64, 4 F32, 2 F16).
+__host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Bytes per link.  SU(2) formats: real entries (8 FUND, 9 ADJ, 4 for a first
+// row) times the storage width (8 F64, 4 F32, 2 F16).  Dense formats: whole
+// 16-byte planes, n^2 complex or real entries packed in order.
 __host__ __device__ constexpr int link_bytes(int rep, int prec)
 {
-    return (is_su2_row(rep) ? 4 : rep == HRD_FUND ? 8 : 9) * (prec == HRD_F64 ? 8 : prec == HRD_F32 ? 4 : 2);
+    return is_dense(rep)
+               ? 16 * ceil_div(ncolour(rep) * ncolour(rep),
+                               (is_real_dense(rep) ? 2 : 1) * (prec == HRD_F64 ? 1 : prec == HRD_F32 ? 2 : 4))
+               : (is_su2_row(rep) ? 4 : rep == HRD_FUND ? 8 : 9) * (prec == HRD_F64 ? 8 : prec == HRD_F32 ? 4 : 2);
 }
 
 // Bytes per site of a spinor: 4N complex components; F16 adds the FP32 site scale.
@@ -725,6 +747,303 @@ struct LinkIO<HRD_ADJ_SU2, R> {
         return l;
     }
 };
+
+// ---------------------------------------------------------------------------
+// Dense links of SU(N > 2) representations: N x N complex (CPLXn) or real
+// (REAL8), entries e = N i + j packed in order into 16-byte planes holding one
+// complex128 / two complex64 / four binary16 complex (CPLXn), or two float64 /
+// four float32 / eight binary16 (REAL8); the last plane is zero-padded.
+// ---------------------------------------------------------------------------
+template <int N, typename R>
+struct CLink {
+    Cx<R> u[N][N];
+};
+template <int N, typename R>
+struct RLink {
+    R r[N][N];
+};
+
+template <int N, typename S>
+struct CplxIO;
+
+template <int N>
+struct CplxIO<N, double> {
+    static constexpr int kPlanes = N * N;
+    using Link = CLink<N, double>;
+    // row I of the link (entries N I .. N I + N - 1)
+    template <int I, bool NT = false>
+    __device__ __forceinline__ static void load_row(const void *U, int Vh, int p, int mu, int site, Cx<double> (&row)[N])
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+#pragma unroll
+        for (int j = 0; j < N; j++) {
+            const vd2 v = ld16d<NT>(b + ((size_t)(N * I + j) * Vh + site) * 16);
+            row[j] = Cx<double>{v.x, v.y};
+        }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        Link l;
+#pragma unroll
+        for (int e = 0; e < N * N; e++) {
+            const vd2 v = ld16d<NT>(b + ((size_t)e * Vh + site) * 16);
+            l.u[e / N][e % N] = Cx<double>{v.x, v.y};
+        }
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const CLink<N, T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+#pragma unroll
+        for (int e = 0; e < N * N; e++)
+            st16d<false>(b + ((size_t)e * Vh + site) * 16, vd2{(double)l.u[e / N][e % N].re, (double)l.u[e / N][e % N].im});
+    }
+};
+
+template <int N>
+struct CplxIO<N, float> {
+    static constexpr int kPlanes = (N * N + 1) / 2;
+    using Link = CLink<N, float>;
+    template <int I, bool NT = false>
+    __device__ __forceinline__ static void load_row(const void *U, int Vh, int p, int mu, int site, Cx<float> (&row)[N])
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        constexpr int e0 = N * I, e1 = N * I + N;
+#pragma unroll
+        for (int q = e0 / 2; q <= (e1 - 1) / 2; q++) {
+            const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
+            if (2 * q >= e0) row[2 * q - e0] = Cx<float>{v.x, v.y};
+            if (2 * q + 1 < e1) row[2 * q + 1 - e0] = Cx<float>{v.z, v.w};
+        }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        Link l;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
+            l.u[(2 * q) / N][(2 * q) % N] = Cx<float>{v.x, v.y};
+            if (2 * q + 1 < N * N) l.u[(2 * q + 1) / N][(2 * q + 1) % N] = Cx<float>{v.z, v.w};
+        }
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const CLink<N, T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            const int e0 = 2 * q, e1 = 2 * q + 1;
+            const Cx<T> a = l.u[e0 / N][e0 % N];
+            const Cx<T> c = e1 < N * N ? l.u[e1 / N][e1 % N] : Cx<T>{0, 0};
+            st16f<false>(b + ((size_t)q * Vh + site) * 16, vf4{(float)a.re, (float)a.im, (float)c.re, (float)c.im});
+        }
+    }
+};
+
+template <int N>
+struct CplxIO<N, h16> {
+    static constexpr int kPlanes = (N * N + 3) / 4;
+    using Link = CLink<N, float>;
+    template <int I, bool NT = false>
+    __device__ __forceinline__ static void load_row(const void *U, int Vh, int p, int mu, int site, Cx<float> (&row)[N])
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        constexpr int e0 = N * I, e1 = N * I + N;
+#pragma unroll
+        for (int q = e0 / 4; q <= (e1 - 1) / 4; q++) {
+            const vh8 v = ld16h<NT>(b + ((size_t)q * Vh + site) * 16);
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (4 * q + j >= e0 && 4 * q + j < e1)
+                    row[4 * q + j - e0] = Cx<float>{(float)v[2 * j], (float)v[2 * j + 1]};
+        }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        Link l;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            const vh8 v = ld16h<NT>(b + ((size_t)q * Vh + site) * 16);
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (4 * q + j < N * N)
+                    l.u[(4 * q + j) / N][(4 * q + j) % N] = Cx<float>{(float)v[2 * j], (float)v[2 * j + 1]};
+        }
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const CLink<N, T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            vh8 v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int e = 4 * q + j;
+                const Cx<T> a = e < N * N ? l.u[e / N][e % N] : Cx<T>{0, 0};
+                v[2 * j] = to_h16(a.re);
+                v[2 * j + 1] = to_h16(a.im);
+            }
+            st16h<false>(b + ((size_t)q * Vh + site) * 16, v);
+        }
+    }
+};
+
+template <int N, typename S>
+struct RealIO {
+    // reals per 16-byte plane: 2 (F64), 4 (F32), 8 (F16)
+    static constexpr int kPer = std::is_same<S, double>::value ? 2 : std::is_same<S, float>::value ? 4 : 8;
+    static constexpr int kPlanes = (N * N + kPer - 1) / kPer;
+    using A = typename Arith<S>::type;
+    using Link = RLink<N, A>;
+    template <int I, bool NT = false>
+    __device__ __forceinline__ static void load_row(const void *U, int Vh, int p, int mu, int site, A (&row)[N])
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        constexpr int e0 = N * I, e1 = N * I + N;
+#pragma unroll
+        for (int q = e0 / kPer; q <= (e1 - 1) / kPer; q++) {
+            const char *a = b + ((size_t)q * Vh + site) * 16;
+            A e[kPer];
+            if constexpr (kPer == 2) {
+                const vd2 v = ld16d<NT>(a);
+                e[0] = v.x;
+                e[1] = v.y;
+            } else if constexpr (kPer == 4) {
+                const vf4 v = ld16f<NT>(a);
+                e[0] = v.x;
+                e[1] = v.y;
+                e[2] = v.z;
+                e[3] = v.w;
+            } else {
+                const vh8 v = ld16h<NT>(a);
+#pragma unroll
+                for (int j = 0; j < 8; j++) e[j] = (float)v[j];
+            }
+#pragma unroll
+            for (int j = 0; j < kPer; j++)
+                if (kPer * q + j >= e0 && kPer * q + j < e1) row[kPer * q + j - e0] = e[j];
+        }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+        Link l;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            const char *a = b + ((size_t)q * Vh + site) * 16;
+            A e[kPer];
+            if constexpr (kPer == 2) {
+                const vd2 v = ld16d<NT>(a);
+                e[0] = v.x;
+                e[1] = v.y;
+            } else if constexpr (kPer == 4) {
+                const vf4 v = ld16f<NT>(a);
+                e[0] = v.x;
+                e[1] = v.y;
+                e[2] = v.z;
+                e[3] = v.w;
+            } else {
+                const vh8 v = ld16h<NT>(a);
+#pragma unroll
+                for (int j = 0; j < 8; j++) e[j] = (float)v[j];
+            }
+#pragma unroll
+            for (int j = 0; j < kPer; j++)
+                if (kPer * q + j < N * N) l.r[(kPer * q + j) / N][(kPer * q + j) % N] = e[j];
+        }
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const RLink<N, T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
+#pragma unroll
+        for (int q = 0; q < kPlanes; q++) {
+            char *a = b + ((size_t)q * Vh + site) * 16;
+            T e[kPer];
+#pragma unroll
+            for (int j = 0; j < kPer; j++) {
+                const int k = kPer * q + j;
+                e[j] = k < N * N ? l.r[k / N][k % N] : T(0);
+            }
+            if constexpr (kPer == 2) {
+                st16d<false>(a, vd2{(double)e[0], (double)e[1]});
+            } else if constexpr (kPer == 4) {
+                st16f<false>(a, vf4{(float)e[0], (float)e[1], (float)e[2], (float)e[3]});
+            } else {
+                vh8 v;
+#pragma unroll
+                for (int j = 0; j < 8; j++) v[j] = to_h16(e[j]);
+                st16h<false>(a, v);
+            }
+        }
+    }
+};
+
+template <typename S>
+struct LinkIO<HRD_CPLX3, S> : CplxIO<3, S> {};
+template <typename S>
+struct LinkIO<HRD_CPLX4, S> : CplxIO<4, S> {};
+template <typename S>
+struct LinkIO<HRD_CPLX6, S> : CplxIO<6, S> {};
+template <typename S>
+struct LinkIO<HRD_REAL8, S> : RealIO<8, S> {};
+
+template <int N, typename R>
+__device__ __forceinline__ void link_mul(const CLink<N, R> &l, const Cx<R> (&h)[N], Cx<R> (&o)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        Cx<R> z = cmul(l.u[i][0], h[0]);
+#pragma unroll
+        for (int j = 1; j < N; j++) z = cfma(l.u[i][j], h[j], z);
+        o[i] = z;
+    }
+}
+template <int N, typename R>
+__device__ __forceinline__ void link_mul_dag(const CLink<N, R> &l, const Cx<R> (&h)[N], Cx<R> (&o)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        Cx<R> z = cmulc(l.u[0][i], h[0]);
+#pragma unroll
+        for (int j = 1; j < N; j++) z = cfmac(l.u[j][i], h[j], z);
+        o[i] = z;
+    }
+}
+template <int N, typename R>
+__device__ __forceinline__ void link_mul(const RLink<N, R> &l, const Cx<R> (&h)[N], Cx<R> (&o)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        Cx<R> z{l.r[i][0] * h[0].re, l.r[i][0] * h[0].im};
+#pragma unroll
+        for (int j = 1; j < N; j++) z = Cx<R>{fmadd(l.r[i][j], h[j].re, z.re), fmadd(l.r[i][j], h[j].im, z.im)};
+        o[i] = z;
+    }
+}
+template <int N, typename R>
+__device__ __forceinline__ void link_mul_dag(const RLink<N, R> &l, const Cx<R> (&h)[N], Cx<R> (&o)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        Cx<R> z{l.r[0][i] * h[0].re, l.r[0][i] * h[0].im};
+#pragma unroll
+        for (int j = 1; j < N; j++) z = Cx<R>{fmadd(l.r[j][i], h[j].re, z.re), fmadd(l.r[j][i], h[j].im, z.im)};
+        o[i] = z;
+    }
+}
 
 // Colour multiplication of one spin component: out = U h, or U^+ h.
 template <typename R>

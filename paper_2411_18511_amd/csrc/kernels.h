@@ -35,6 +35,10 @@ hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a,
 // is not stored; instead r <- r - alpha out and ||r||^2 partials are written
 // (one per block, hop_blocks(g) of them).
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov = CLOV_NONE);
+// the same for the dense SU(N > 2) formats (no clover), dslash_sun.hip
+hipError_t launch_hop_dense(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
+                            hipStream_t st);
+hipError_t launch_hop_rupdate_dense(int rep, int prec, const HopArgs &a, hipStream_t st);
 
 // ----- field preparation (pack.hip) ----------------------------------------
 hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,
@@ -47,6 +51,14 @@ hipError_t launch_convert_gauge(int rep, const Geom &g, const void *U64, void *U
 // nparity blocks of Vh sites, ncomp complex components per site
 hipError_t launch_convert_spinor(int Vh, int nparity, int ncomp, bool to_f32, const void *in, void *out,
                                  hipStream_t st);
+// dense SU(N > 2) formats (pack_sun.hip): natural <-> packed, F64 -> F32/F16,
+// and the representations of fundamental SU(nc) links (CPLXnc, F64) in the
+// format of the representation (F64): kind 0 fund, 1 adj, 2 sym, 3 asym
+hipError_t launch_pack_gauge_dense(int rep, int prec, const Geom &g, const void *nat, void *packed, bool unpack,
+                                   hipStream_t st);
+hipError_t launch_convert_gauge_dense(int rep, int prec_out, const Geom &g, const void *U64, void *Uout,
+                                      hipStream_t st);
+hipError_t launch_represent_sun(int nc, int kind, const Geom &g, const void *Uf, void *Ur, hipStream_t st);
 // F64 links -> F16 links
 hipError_t launch_convert_gauge_h16(int rep, const Geom &g, const void *U64, void *U16, hipStream_t st);
 // spinor storage conversion between any two precisions (same precision: copy)

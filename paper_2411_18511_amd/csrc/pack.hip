@@ -340,6 +340,18 @@ inline dim3 grid_for(long n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)
 
 }  // namespace
 
+namespace {
+
+template <int N>
+void pack_spinor_n(int prec, dim3 grid, hipStream_t st, const Geom &g, int p0, int np, const Cx<double> *n, char *pk,
+                   bool unpack)
+{
+    if (prec == HRD_F64) hipLaunchKernelGGL((pack_spinor_kernel<N, double>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
+    else hipLaunchKernelGGL((pack_spinor_kernel<N, float>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
+}
+
+}  // namespace
+
 hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,
                               bool unpack, hipStream_t st)
 {
@@ -348,12 +360,12 @@ hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const
     const dim3 grid = grid_for((long)np * g.Vh);
     const Cx<double> *n = reinterpret_cast<const Cx<double> *>(nat);
     char *pk = reinterpret_cast<char *>(packed);
-    if (ncolour(rep) == 2) {
-        if (prec == HRD_F64) hipLaunchKernelGGL((pack_spinor_kernel<2, double>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
-        else hipLaunchKernelGGL((pack_spinor_kernel<2, float>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
-    } else {
-        if (prec == HRD_F64) hipLaunchKernelGGL((pack_spinor_kernel<3, double>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
-        else hipLaunchKernelGGL((pack_spinor_kernel<3, float>), grid, dim3(kBlock), 0, st, g, p0, np, n, pk, unpack);
+    switch (ncolour(rep)) {
+        case 2: pack_spinor_n<2>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        case 3: pack_spinor_n<3>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        case 4: pack_spinor_n<4>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        case 6: pack_spinor_n<6>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        default: pack_spinor_n<8>(prec, grid, st, g, p0, np, n, pk, unpack); break;
     }
     return hipGetLastError();
 }
@@ -361,6 +373,7 @@ hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const
 hipError_t launch_pack_gauge(int rep, int prec, const Geom &g, const void *nat, void *packed, bool unpack,
                              hipStream_t st)
 {
+    if (is_dense(rep)) return launch_pack_gauge_dense(rep, prec, g, nat, packed, unpack, st);
     const dim3 grid = grid_for(8L * g.Vh);
     if (is_su2_row(rep)) {
         Cx<double> *n = reinterpret_cast<Cx<double> *>(const_cast<void *>(nat));
@@ -394,6 +407,7 @@ hipError_t launch_represent_backward(const Geom &g, const void *Uf, const void *
 
 hipError_t launch_convert_gauge(int rep, const Geom &g, const void *U64, void *U32, hipStream_t st)
 {
+    if (is_dense(rep)) return launch_convert_gauge_dense(rep, HRD_F32, g, U64, U32, st);
     const dim3 grid = grid_for(8L * g.Vh);
     if (is_su2_row(rep)) hipLaunchKernelGGL(convert_gauge_su2_kernel, grid, dim3(kBlock), 0, st, g, U64, U32);
     else if (rep == HRD_FUND) hipLaunchKernelGGL((convert_gauge_kernel<HRD_FUND>), grid, dim3(kBlock), 0, st, g, U64, U32);
@@ -411,6 +425,7 @@ hipError_t launch_convert_spinor(int Vh, int nparity, int ncomp, bool to_f32, co
 
 hipError_t launch_convert_gauge_h16(int rep, const Geom &g, const void *U64, void *U16, hipStream_t st)
 {
+    if (is_dense(rep)) return launch_convert_gauge_dense(rep, HRD_F16, g, U64, U16, st);
     const dim3 grid = grid_for(8L * g.Vh);
     switch (rep) {
         case HRD_FUND: hipLaunchKernelGGL((convert_gauge_h16_kernel<HRD_FUND>), grid, dim3(kBlock), 0, st, g, U64, U16); break;
@@ -466,8 +481,13 @@ hipError_t launch_convert_spinor_prec(int rep, int Vh, int nparity, int prec_in,
     const size_t ib = (size_t)Vh * spinor_site_bytes(rep, prec_in);
     const size_t ob = (size_t)Vh * spinor_site_bytes(rep, prec_out);
     if (prec_in == prec_out) return launch_copy(ib * nparity, in, out, st);
-    if (ncolour(rep) == 2) convert_nc<8>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st);
-    else convert_nc<12>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st);
+    switch (ncolour(rep)) {
+        case 2: convert_nc<8>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case 3: convert_nc<12>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case 4: convert_nc<16>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case 6: convert_nc<24>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        default: convert_nc<32>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+    }
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ _lib = ctypes.CDLL(LIBPATH)
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
 FUND, ADJ, FUND_SU2, ADJ_SU2 = 0, 1, 2, 3
+CPLX3, CPLX4, CPLX6, REAL8 = 4, 5, 6, 7
+SUN_FUND, SUN_ADJ, SUN_SYM, SUN_ASYM = 0, 1, 2, 3
 F64, F32, F16 = 0, 1, 2
 FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
 SITES_ALL, SITES_EVEN, SITES_ODD = 0, 1, 2
@@ -36,7 +38,13 @@ CG_F64, CG_MIXED, CG_MIXED16 = 0, 1, 2
 _STATUS_NAMES = {0: "HRD_OK", 1: "HRD_EINVAL", 2: "HRD_ESHAPE", 3: "HRD_EALIAS", 4: "HRD_EHIP",
                  5: "HRD_ENOCONV", 6: "HRD_EBREAKDOWN", 7: "HRD_ESIZE"}
 _REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, "fund_su2": FUND_SU2,
-         "adj_su2": ADJ_SU2, FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2}
+         "adj_su2": ADJ_SU2, "cplx3": CPLX3, "cplx4": CPLX4, "cplx6": CPLX6, "real8": REAL8,
+         # SU(N > 2) representations by name -> their link formats
+         "su3_fund": CPLX3, "su3_asym": CPLX3, "su3_sym": CPLX6, "su3_adj": REAL8, "su4_fund": CPLX4,
+         "su4_asym": CPLX6,
+         FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2, CPLX3: CPLX3, CPLX4: CPLX4, CPLX6: CPLX6,
+         REAL8: REAL8}
+_SUN_KINDS = {"fund": SUN_FUND, "adj": SUN_ADJ, "sym": SUN_SYM, "asym": SUN_ASYM}
 _PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "f16": F16, "fp16": F16, F64: F64, F32: F32,
           F16: F16, torch.float64: F64, torch.float32: F32}
 _PARITIES = {"full": FULL, "eo": EO, "hop_eo": HOP_EO, "hop_oe": HOP_OE,
@@ -102,6 +110,8 @@ _sig("hrd_pack_gauge", _I, _LP, _I, _I, _P, _P, _P)
 _sig("hrd_unpack_gauge", _I, _LP, _I, _I, _P, _P, _P)
 _sig("hrd_represent", _I, _LP, _P, _P, _I, _P)
 _sig("hrd_represent_backward", _I, _LP, _P, _P, _P, _P)
+_sig("hrd_sun_rep_format", _I, _I, _I)
+_sig("hrd_represent_sun", _I, _LP, _I, _I, _P, _P, _P)
 _sig("hrd_convert_gauge", _I, _LP, _I, _P, _P, _P)
 _sig("hrd_pack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
 _sig("hrd_unpack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
@@ -199,13 +209,16 @@ class Geometry:
 
 
 def ncolour(rep):
-    """Colours of the fermion: 2 for the fundamental formats, 3 for the adjoint ones."""
-    return 2 if _REPS[rep] in (FUND, FUND_SU2) else 3
+    """Colours of the fermion in a link format (2, 3, 4, 6 or 8)."""
+    return {FUND: 2, FUND_SU2: 2, ADJ: 3, ADJ_SU2: 3, CPLX3: 3, CPLX4: 4, CPLX6: 6, REAL8: 8}[_REPS[rep]]
 
 
 def base_rep(rep):
     """Uncompressed representation whose gauge layout derivatives use."""
-    return FUND if ncolour(rep) == 2 else ADJ
+    r = _REPS[rep]
+    if r >= CPLX3:
+        return r
+    return FUND if ncolour(r) == 2 else ADJ
 
 
 def spinor_bytes(dims, rep, prec, nparity):
@@ -230,10 +243,14 @@ def pack_gauge(U_nat, dims, rep, prec):
 def unpack_gauge(U, dims, rep, prec):
     rep, prec = _REPS[rep], _PRECS[prec]
     V = Geometry(tuple(dims), rep).volume
-    if rep != ADJ:
-        out = torch.empty((4, V, 2, 2), dtype=torch.complex128, device=U.device)
+    if rep in (ADJ, REAL8):
+        n = ncolour(rep)
+        out = torch.empty((4, V, n, n), dtype=torch.float64, device=U.device)
+    elif rep >= CPLX3:
+        n = ncolour(rep)
+        out = torch.empty((4, V, n, n), dtype=torch.complex128, device=U.device)
     else:
-        out = torch.empty((4, V, 3, 3), dtype=torch.float64, device=U.device)
+        out = torch.empty((4, V, 2, 2), dtype=torch.complex128, device=U.device)
     _check(_lib.hrd_unpack_gauge(ctypes.byref(lattice(dims)), rep, prec, _ptr(U), _ptr(out), _stream()))
     return out
 
@@ -242,6 +259,24 @@ def represent(U_fund, dims, prec=F64):
     prec = _PRECS[prec]
     out = _empty(gauge_bytes(dims, ADJ, prec), U_fund.device)
     _check(_lib.hrd_represent(ctypes.byref(lattice(dims)), _ptr(U_fund), _ptr(out), prec, _stream()))
+    return out
+
+
+def sun_rep_format(nc, kind):
+    """Link format of representation kind ('fund', 'adj', 'sym', 'asym') of SU(nc), or None."""
+    r = _lib.hrd_sun_rep_format(int(nc), _SUN_KINDS[kind])
+    return None if r < 0 else r
+
+
+def represent_sun(U_fund64, dims, nc, kind):
+    """Packed FP64 links of representation kind of SU(nc) from the packed FP64
+    fundamental field (format CPLX3 / CPLX4)."""
+    fmt = sun_rep_format(nc, kind)
+    if fmt is None:
+        raise ValueError(f"no link format for SU({nc}) {kind}")
+    out = _empty(gauge_bytes(dims, fmt, F64), U_fund64.device)
+    _check(_lib.hrd_represent_sun(ctypes.byref(lattice(dims)), int(nc), _SUN_KINDS[kind], _ptr(U_fund64), _ptr(out),
+                                  _stream()))
     return out
 
 

@@ -22,7 +22,9 @@ Table 1); bandwidth does not depend on field content, so these stand in:
   factorisation of a complex Gaussian matrix with the phases of R's diagonal
   divided out (Mezzadri's method), then divided by an N-th root of the
   determinant; "smeared" SU(N) links are exp(i eps H) with H a Gaussian
-  traceless Hermitian matrix (near the identity).
+  traceless Hermitian matrix (near the identity); "product" SU(N) links are
+  products of Haar SU(2) elements embedded in every 2x2 block (fast to draw
+  on large lattices).
 * Spinors: real and imaginary parts i.i.d. N(0, 1/2).
 """
 import numpy as np
@@ -113,6 +115,22 @@ def smeared_sun(rng, shape, nc, eps=0.35):
     return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * eps * w), np.conj(v))
 
 
+def subgroup_product_sun(rng, shape, nc):
+    """SU(nc) matrices as products of Haar SU(2) elements embedded in every
+    (i, j) 2x2 block, i < j (cheap to draw for large lattices; not Haar on
+    SU(nc), but spread over the group)."""
+    shape = tuple(shape)
+    U = np.broadcast_to(np.eye(nc, dtype=np.complex128), shape + (nc, nc)).copy()
+    for i in range(nc):
+        for j in range(i + 1, nc):
+            s2 = haar_su2(rng, shape)
+            # right-multiply by the embedded block: columns i and j of U mix
+            ci, cj = U[..., :, i].copy(), U[..., :, j].copy()
+            U[..., :, i] = ci * s2[..., 0, 0, None] + cj * s2[..., 1, 0, None]
+            U[..., :, j] = ci * s2[..., 0, 1, None] + cj * s2[..., 1, 1, None]
+    return U
+
+
 def gauge_field_sun(dims, seed, nc, kind="haar"):
     """Fundamental SU(nc) gauge field [4, T, L1, L2, L3, nc, nc] (complex128)."""
     if nc == 2:
@@ -123,6 +141,8 @@ def gauge_field_sun(dims, seed, nc, kind="haar"):
         return haar_sun(rng, shape, nc)
     if kind == "smeared":
         return smeared_sun(rng, shape, nc)
+    if kind == "product":
+        return subgroup_product_sun(rng, shape, nc)
     if kind == "unit":
         return np.broadcast_to(np.eye(nc, dtype=np.complex128), shape + (nc, nc)).copy()
     raise ValueError(f"unknown gauge kind {kind!r}")

@@ -79,3 +79,45 @@ class Field:
     def unpack(self, packed, prec="f64", sites="all"):
         out = hrd().unpack_spinor(packed, self.dims, self.rep, prec, sites)
         return from_dev_spinor(out, self.dims)
+
+
+class FieldSUN:
+    """A seeded SU(nc) problem in representation `rep` ('fund', 'adj', 'sym',
+    'asym'): fundamental links packed on the GPU (format CPLXnc), the
+    representation built by the library, FP32 and F16 copies; the oracle gets
+    the representation computed by its own map."""
+
+    def __init__(self, dims, nc, rep, seed, kind="haar"):
+        import oracle as O
+
+        h = hrd()
+        self.dims = tuple(dims)
+        self.nc = nc
+        self.fmt = h.sun_rep_format(nc, rep)
+        self.rep = self.fmt
+        self.n = h.ncolour(self.fmt)
+        self.Uf = inputs.gauge_field_sun(dims, seed, nc, kind=kind)
+        Uf64 = h.pack_gauge(to_dev_gauge(self.Uf), dims, "cplx3" if nc == 3 else "cplx4", "f64")
+        self.U64 = h.represent_sun(Uf64, dims, nc, rep)
+        self.U32 = h.convert_gauge_prec(self.U64, dims, self.fmt, "f32")
+        self.U16 = h.convert_gauge_prec(self.U64, dims, self.fmt, "f16")
+        self.U_orc = O.represent(self.Uf, rep).astype(np.complex128)
+
+    def spinor(self, seed):
+        return inputs.gaussian_spinor(self.dims, self.n, seed)
+
+    def pack(self, psi, prec="f64", sites="all"):
+        h = hrd()
+        if prec == "f16":
+            np_ = 2 if sites == "all" else 1
+            return h.convert_spinor_prec(h.pack_spinor(to_dev_spinor(psi), self.dims, self.fmt, "f64", sites),
+                                         self.dims, self.fmt, np_, "f64", "f16")
+        return h.pack_spinor(to_dev_spinor(psi), self.dims, self.fmt, prec, sites)
+
+    def unpack(self, packed, prec="f64", sites="all"):
+        h = hrd()
+        if prec == "f16":
+            np_ = 2 if sites == "all" else 1
+            packed = h.convert_spinor_prec(packed, self.dims, self.fmt, np_, "f16", "f64")
+            prec = "f64"
+        return from_dev_spinor(h.unpack_spinor(packed, self.dims, self.fmt, prec, sites), self.dims)

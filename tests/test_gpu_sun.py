@@ -1,0 +1,140 @@
+"""GPU parity for SU(N > 2) with fermions in the fundamental, adjoint and
+two-index representations (Sec. 1), through the dense link formats CPLX3,
+CPLX4, CPLX6 and REAL8.
+
+* the library's representation of fundamental SU(3) / SU(4) links equals the
+  oracle's map entry by entry (same bases) to FP64 rounding; pack/unpack of
+  the dense formats round-trips exactly in FP64;
+* D, D^ and the hop blocks with daggers equal the oracle on the oracle's own
+  representation links: 1e-13 (FP64), 1e-6 (FP32), and for F16 the
+  per-component / norm-wise bounds of the 16-bit format (oracle on the
+  F16-rounded links and spinors);
+* FP64, mixed and MIXED16 CG reach a true residual <= 1e-10 (oracle
+  recomputation).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import FieldSUN, requires_gpu, rel_err, hrd, to_dev_gauge
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+CASES = [(3, "fund"), (3, "adj"), (3, "sym"), (3, "asym"), (4, "fund"), (4, "asym")]
+LATS = [(4, 4, 4, 4), (6, 4, 6, 10)]
+
+
+@pytest.fixture(scope="module")
+def oracle():
+    import oracle as O
+
+    O._load()
+    return O
+
+
+@pytest.mark.parametrize("nc,rep", CASES)
+def test_represent_and_pack(oracle, nc, rep):
+    h = hrd()
+    dims = (4, 2, 4, 6)
+    F = FieldSUN(dims, nc, rep, seed=3)
+    got = h.unpack_gauge(F.U64, dims, F.fmt, "f64").cpu().numpy()
+    V = int(np.prod(dims))
+    want = F.U_orc.reshape(4, V, F.n, F.n)
+    if F.fmt == h.REAL8:
+        want = want.real
+    assert np.abs(got - want).max() < 1e-14
+    # natural -> packed -> natural is exact in FP64
+    nat = torch.from_numpy(np.ascontiguousarray(got)).cuda()
+    again = h.unpack_gauge(h.pack_gauge(nat, dims, F.fmt, "f64"), dims, F.fmt, "f64").cpu().numpy()
+    assert np.array_equal(again, got)
+    # FP32 copy unpacks to the FP32 rounding
+    g32 = h.unpack_gauge(F.U32, dims, F.fmt, "f32").cpu().numpy()
+    if np.iscomplexobj(got):
+        assert np.array_equal(g32.real, got.real.astype(np.float32).astype(np.float64))
+        assert np.array_equal(g32.imag, got.imag.astype(np.float32).astype(np.float64))
+    else:
+        assert np.array_equal(g32, got.astype(np.float32).astype(np.float64))
+
+
+def _round16_rep_links(F, oracle):
+    """The library's F16 links as the oracle reads them: each entry of the
+    library's FP64 representation links rounded through FP32 to binary16."""
+    h = hrd()
+    V = int(np.prod(F.dims))
+    U = h.unpack_gauge(F.U64, F.dims, F.fmt, "f64").cpu().numpy().reshape((4,) + F.dims + (F.n, F.n))
+    return oracle.round_links16(U).astype(np.complex128)
+
+
+@pytest.mark.parametrize("nc,rep,dims", [(nc, r, d) for nc, r in CASES for d in LATS])
+def test_operator_sun(oracle, nc, rep, dims):
+    h = hrd()
+    m0 = -0.3
+    m = 4.0 + m0
+    F = FieldSUN(dims, nc, rep, seed=11)
+    U = F.U_orc
+    psi = F.spinor(12)
+    pe, po = oracle.restrict(psi, 0), oracle.restrict(psi, 1)
+    for dagger in (False, True):
+        want = {
+            "full": (oracle.dirac_dagger if dagger else oracle.dirac)(U, psi, m0),
+            "eo": (oracle.dhat_dagger if dagger else oracle.dhat)(U, pe, m0),
+            "hop_eo": (oracle.hop_block_dagger if dagger else oracle.hop_block)(U, po, 0),
+            "hop_oe": (oracle.hop_block_dagger if dagger else oracle.hop_block)(U, pe, 1),
+        }
+        src = {"full": (psi, "all"), "eo": (pe, "even"), "hop_eo": (po, "odd"), "hop_oe": (pe, "even")}
+        osites = {"full": "all", "eo": "even", "hop_eo": "even", "hop_oe": "odd"}
+        for prec, Ug, tol in (("f64", F.U64, 1e-13), ("f32", F.U32, 1e-6)):
+            for par in ("full", "eo", "hop_eo", "hop_oe"):
+                x, sites = src[par]
+                out = h.dirac_apply(Ug, F.pack(x, prec, sites), m0, F.fmt, par, dims, prec=prec, dagger=dagger)
+                w = want[par]
+                if par == "hop_eo":
+                    w = oracle.restrict(w, 0)
+                if par == "hop_oe":
+                    w = oracle.restrict(w, 1)
+                err = rel_err(F.unpack(out, prec, osites[par]), w)
+                assert err <= tol, (prec, par, dagger, err)
+        # F16: oracle on the F16-rounded inputs, norm-wise bound of the 16-bit format
+        Uq = _round16_rep_links(F, oracle)
+        psiq = oracle.round_spinor16(psi)
+        peq = oracle.restrict(psiq, 0)
+        eps = 2.0 ** -12 * np.sqrt(8 * F.n)
+        out = h.dirac_apply(F.U16, F.pack(psi, "f16", "all"), m0, F.fmt, "full", dims, prec="f16", dagger=dagger)
+        w = (oracle.dirac_dagger if dagger else oracle.dirac)(Uq, psiq, m0)
+        err = oracle.norm(F.unpack(out, "f16", "all") - w)
+        assert err <= eps * oracle.norm(w) + 1e-5 * oracle.norm(w), ("f16 full", dagger)
+        out = h.dirac_apply(F.U16, F.pack(pe, "f16", "even"), m0, F.fmt, "eo", dims, prec="f16", dagger=dagger)
+        w = (oracle.dhat_dagger if dagger else oracle.dhat)(Uq, peq, m0)
+        err = oracle.norm(F.unpack(out, "f16", "even") - w)
+        bound = eps * (oracle.norm(w) + 16 * oracle.norm(peq) / m) + 1e-5 * oracle.norm(w)
+        assert err <= bound, ("f16 eo", dagger, err, bound)
+
+
+@pytest.mark.parametrize("nc,rep", CASES)
+@pytest.mark.parametrize("mode", ["f64", "mixed", "mixed16"])
+def test_cg_sun(oracle, nc, rep, mode):
+    h = hrd()
+    dims, m0 = (6, 4, 6, 10), -0.3
+    F = FieldSUN(dims, nc, rep, seed=21, kind="smeared")
+    b_np = oracle.restrict(F.spinor(22), 0)
+    b = F.pack(b_np, "f64", "even")
+    Ulo = {"f64": None, "mixed": F.U32, "mixed16": F.U16}[mode]
+    x, info = h.cg_solve(F.U64, b, m0, 1e-10, dims, F.fmt, mode=mode, U32=Ulo)
+    assert info["status"] == "HRD_OK" and info["true_rel_residual"] <= 1e-10
+    xg = F.unpack(x, "f64", "even")
+    assert oracle.true_residual(F.U_orc, b_np, xg, m0) <= 1e-10
+
+
+def test_sun_errors():
+    h = hrd()
+    dims = (4, 4, 4, 4)
+    assert h.sun_rep_format(4, "sym") is None and h.sun_rep_format(5, "fund") is None
+    F = FieldSUN(dims, 3, "sym", seed=31)
+    psi = F.pack(F.spinor(32), "f64", "all")
+    # the force, clover and batched paths take the SU(2) formats only
+    with pytest.raises(h.HrdError) as e:
+        h.dirac_force(F.U64, psi, psi, dims, F.fmt)
+    assert e.value.status == h.EINVAL
+    with pytest.raises(h.HrdError) as e:
+        h.clover_build(F.U64, 1.0, -0.2, dims, F.fmt)
+    assert e.value.status == h.EINVAL
