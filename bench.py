@@ -79,8 +79,9 @@ def dhat_clover_alg_bytes(V, rep, prec):
     return dhat_alg_bytes(V, rep, prec) + V * clover_site_bytes(rep, prec)
 
 
-KERNEL_SOURCES = ["paper_2411_18511_amd/csrc/dslash.hip", "paper_2411_18511_amd/csrc/common.h",
-                  "paper_2411_18511_amd/csrc/spin.h"]
+KERNEL_SOURCES = ["paper_2411_18511_amd/csrc/hop.h", "paper_2411_18511_amd/csrc/dslash.hip",
+                  "paper_2411_18511_amd/csrc/common.h", "paper_2411_18511_amd/csrc/spin.h",
+                  "paper_2411_18511_amd/csrc/clover.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_fund_48x48x48x48.traffic.json")
 
 
