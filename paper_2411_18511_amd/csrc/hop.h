@@ -39,12 +39,31 @@
 #ifndef HRD_HOP_BLOCK
 #define HRD_HOP_BLOCK 256
 #endif
+// SU(2) formats: 0 lets the compiler overlap all eight direction terms; 1
+// fences after each direction (forward and backward term), 2 after each term,
+// 3 after every second direction.
+#ifndef HRD_FENCE
+#define HRD_FENCE 0
+#endif
 
 namespace hrd {
 
 constexpr int kHopBlock = HRD_HOP_BLOCK;  // threads per workgroup of the hopping kernel
 
 namespace {
+
+// Barrier between the direction terms of the dense formats: the accumulator
+// is pinned in registers (each component passes through an empty asm
+// statement) and memory operations are ordered, so one direction's products
+// are finished before the next direction's loads issue.  Without it the
+// compiler issues the loads of all eight terms first and defers their
+// arithmetic, which needs the spinors and links of every term live at once.
+template <typename R, int NC>
+__device__ __forceinline__ void dir_fence(Cx<R> (&acc)[NC])
+{
+#pragma unroll
+    for (int k = 0; k < NC; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im)::"memory");
+}
 
 // S: storage type of the source spinor and the links; R: arithmetic type.
 template <int MU, bool DAG, int REP, typename S, typename R = typename Arith<S>::type>
@@ -75,6 +94,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         link_mul(l, h1, u1);
         reconstruct<MU, SF, N, R>(acc, u0, u1);
     }
+    if constexpr (HRD_FENCE == 2) dir_fence(acc);
     {
         const int j = nbr_bwd(g, s, MU);
         Cx<R> psi[NC];
@@ -174,19 +194,6 @@ __device__ __forceinline__ void dense_mul_dag_rows(const void *U, int Vh, int p,
     }
 }
 
-// Barrier between the direction terms of the dense formats: the accumulator
-// is pinned in registers (each component passes through an empty asm
-// statement) and memory operations are ordered, so one direction's products
-// are finished before the next direction's loads issue.  Without it the
-// compiler issues the loads of all eight terms first and defers their
-// arithmetic, which needs the spinors and links of every term live at once.
-template <typename R, int NC>
-__device__ __forceinline__ void dir_fence(Cx<R> (&acc)[NC])
-{
-#pragma unroll
-    for (int k = 0; k < NC; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im)::"memory");
-}
-
 // One direction of the stencil for the dense formats (same arithmetic as
 // hop_dir, links streamed by row).
 template <int MU, bool DAG, int REP, typename S, typename R = typename Arith<S>::type>
@@ -284,8 +291,11 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             hop_dir_dense<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         } else {
             hop_dir<0, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
             hop_dir<1, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            if constexpr (HRD_FENCE >= 1) dir_fence(acc);
             hop_dir<2, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
             hop_dir<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         }
         const R cb = (R)a.b;
