@@ -195,14 +195,15 @@ def mixed_volume_cg(torch, hrd, inputs, dev, nrhs=12, tol=1e-10):
             "iters_batched_max": max(i["iters"] for i in infos), "iters_single_max": max(seq_iters)}
 
 
-SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx6": 36 * 16, "real8": 64 * 8}  # FP64, unpadded
+SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx6": 36 * 16, "real8": 64 * 8, "su3_row2": 6 * 16}  # FP64, unpadded
 
 
 def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10, m0=-0.3):
     """SU(3) with fermions in the fundamental (CPLX3), 2-index symmetric (CPLX6)
     and adjoint (REAL8) representations: representation build, hopping block
     in FP64 / FP32 / F16 and even/odd D^ in FP32 (algorithmic bytes on
-    unpadded links), and mixed / MIXED16 CG to 1e-10 for the fundamental."""
+    unpadded links), and mixed / MIXED16 CG to 1e-10 for the fundamental; the
+    fundamental also in the two-row format."""
     V = int(np.prod(dims))
     Uf = inputs.gauge_field_sun(dims, 7, 3, kind="product")
     Uf_dev = torch.from_numpy(Uf.reshape(4, V, 3, 3)).to(dev)
@@ -211,14 +212,21 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
     del Uf_dev
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     out = {"dims": list(dims), "group": "SU(3)", "links": "products of embedded Haar SU(2) elements"}
-    for rep in ("fund", "sym", "adj"):
-        fmt = hrd.sun_rep_format(3, rep)
-        name = {hrd.CPLX3: "cplx3", hrd.CPLX6: "cplx6", hrd.REAL8: "real8"}[fmt]
-        n = hrd.ncolour(fmt)
+    for rep in ("fund", "sym", "adj", "fund_row2"):
         a, b = ev(), ev()
-        a.record()
-        U64 = hrd.represent_sun(Uf64, dims, 3, rep)
-        b.record()
+        if rep == "fund_row2":
+            # the same SU(3) links stored as two rows (third row rebuilt in the kernel)
+            fmt, name = hrd.SU3_ROW2, "su3_row2"
+            a.record()
+            U64 = hrd.pack_gauge(hrd.unpack_gauge(Uf64, dims, "cplx3", "f64"), dims, fmt, "f64")
+            b.record()
+        else:
+            fmt = hrd.sun_rep_format(3, rep)
+            name = {hrd.CPLX3: "cplx3", hrd.CPLX6: "cplx6", hrd.REAL8: "real8"}[fmt]
+            a.record()
+            U64 = hrd.represent_sun(Uf64, dims, 3, rep)
+            b.record()
+        n = hrd.ncolour(fmt)
         b.synchronize()
         r = {"format": name, "N_R": n, "represent_ms": a.elapsed_time(b)}
         psi = torch.from_numpy(inputs.gaussian_spinor(dims, n, 8).reshape(V, 4, n)).to(dev)
@@ -255,7 +263,7 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
                 alg = V * 8 * L + (V // 2) * 5 * S
                 r["dhat_f32"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
                                  "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-            if rep == "fund" and prec != "f64":
+            if rep in ("fund", "fund_row2") and prec != "f64":
                 mode = "mixed" if prec == "f32" else "mixed16"
                 a.record()
                 _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode=mode, U32=Ug)
@@ -263,7 +271,7 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
                 b.synchronize()
                 r[f"cg_{mode}"] = {"ms": a.elapsed_time(b), **info}
             del Ug, so, se, dst
-        if rep == "fund":
+        if rep in ("fund", "fund_row2"):
             a.record()
             _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode="f64")
             b.record()

@@ -74,6 +74,11 @@
  *                    entry are padding (written as zero).
  *     link REAL8 (8 x 8 real, entry e = 8 i + j): F64 32 planes of 2 float64,
  *                    F32 16 planes of 4 float32, F16 8 planes of 8 binary16.
+ *     link SU3_ROW2 (rows 0 and 1 of an SU(3) link, entries U00 U01 U02 U10
+ *                    U11 U12): F64 6 planes of complex128, F32 3 planes of
+ *                    2 x complex64, F16 1 plane of 4 complex (U00 .. U10) as
+ *                    8 binary16 then 1 plane of 2 complex (U11, U12) as 4
+ *                    binary16.  Natural layout: complex128 [4][V][3][3].
  *   A full-lattice spinor is [parity][planes][Vh], even block first.  A
  *   gauge field is [parity][mu][planes][Vh]: block (p, mu) holds the links
  *   U_mu(x) of the sites x of parity p.
@@ -142,7 +147,10 @@ typedef enum {
     HRD_CPLX3 = 4,
     HRD_CPLX4 = 5,
     HRD_CPLX6 = 6,
-    HRD_REAL8 = 7
+    HRD_REAL8 = 7,
+    /* SU(3) fundamental links stored as their first two rows; the third row
+       is conj(row0 x row1), exact for SU(3) matrices (assumed). */
+    HRD_SU3_ROW2 = 8
 } hrd_rep;
 /* Storage precision of a field.  HRD_F16 is the 16-bit storage of the mixed
    solver's inner iterations (binary16 values, FP32 arithmetic; spinors carry
@@ -220,7 +228,8 @@ hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj
 /* Representations of SU(N > 2) (Sec. 1).  kind selects the representation;
    hrd_sun_rep_format returns the link format of (nc, kind), or -1 when none
    exists:  SU(3): FUND -> HRD_CPLX3, ADJ -> HRD_REAL8, SYM -> HRD_CPLX6,
-   ASYM -> HRD_CPLX3;  SU(4): FUND -> HRD_CPLX4, ASYM -> HRD_CPLX6.
+   ASYM -> HRD_CPLX3;  SU(4): FUND -> HRD_CPLX4, ASYM -> HRD_CPLX6.  (SU(3)
+   fundamental links may also be packed directly as HRD_SU3_ROW2.)
    Bases: ADJ R_ab = 2 Re tr(T_a U T_b U^+) with T_a the generalised Gell-Mann
    matrices halved, ordered pairwise (j < k: symmetric then antisymmetric)
    then diagonal diag(1, .., 1, -l, 0, ..) / sqrt(2 l (l + 1)); SYM / ASYM

@@ -61,7 +61,7 @@ hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec)
 
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
 {
-    if (rep < HRD_FUND || rep > HRD_REAL8) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
+    if (rep < HRD_FUND || rep > HRD_SU3_ROW2) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
     if (prec != HRD_F64 && prec != HRD_F32) return fail(HRD_EINVAL, "invalid precision %d", (int)prec);
     return HRD_OK;
 }
@@ -849,7 +849,6 @@ hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 {
     (void)U;
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_dirac_force"));
     HRD_TRY(check_rep_prec(rep, prec));
     if (prec != HRD_F64) return fail(HRD_EINVAL, "the force is computed in FP64 only");
     if (!X || !Y || !F) return fail(HRD_EINVAL, "NULL field pointer");
@@ -862,7 +861,7 @@ hrd_status hrd_dirac_force(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 
 size_t hrd_action_force_workspace_bytes(const hrd_lattice *lat, hrd_rep rep)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK || is_dense(rep)) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, HRD_F64) != HRD_OK) return 0;
     return 2 * spinor_bytes(lat, rep, HRD_F64, 2) + 256;
 }
 
@@ -870,7 +869,6 @@ hrd_status hrd_action_force(const hrd_lattice *lat, hrd_rep rep, const void *U, 
                             double scale, void *work, size_t work_bytes, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_action_force"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!U || !xi || !F || !work) return fail(HRD_EINVAL, "NULL pointer");
     if (!std::isfinite(m0) || 4.0 + m0 == 0.0) return fail(HRD_EINVAL, "invalid m0 %g", m0);

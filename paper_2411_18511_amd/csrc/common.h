@@ -420,7 +420,7 @@ __host__ __device__ constexpr bool is_su2_row(int rep) { return rep == HRD_FUND_
 __host__ __device__ constexpr int ncolour(int rep)
 {
     return (rep == HRD_FUND || rep == HRD_FUND_SU2) ? 2
-           : (rep == HRD_ADJ || rep == HRD_ADJ_SU2 || rep == HRD_CPLX3) ? 3
+           : (rep == HRD_ADJ || rep == HRD_ADJ_SU2 || rep == HRD_CPLX3 || rep == HRD_SU3_ROW2) ? 3
            : rep == HRD_CPLX4 ? 4
            : rep == HRD_CPLX6 ? 6
            : 8;
@@ -435,7 +435,7 @@ __host__ __device__ constexpr bool is_real_dense(int rep) { return rep == HRD_RE
 // itself for the dense formats.
 __host__ __device__ constexpr int base_rep(int rep)
 {
-    return is_dense(rep) ? rep : ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ;
+    return rep == HRD_SU3_ROW2 ? HRD_CPLX3 : is_dense(rep) ? rep : ncolour(rep) == 2 ? HRD_FUND : HRD_ADJ;
 }
 
 __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -445,7 +445,8 @@ __host__ __device__ constexpr int ceil_div(int a, int b) { return (a + b - 1) / 
 // 16-byte planes, n^2 complex or real entries packed in order.
 __host__ __device__ constexpr int link_bytes(int rep, int prec)
 {
-    return is_dense(rep)
+    return rep == HRD_SU3_ROW2 ? (prec == HRD_F64 ? 96 : prec == HRD_F32 ? 48 : 24)
+           : is_dense(rep)
                ? 16 * ceil_div(ncolour(rep) * ncolour(rep),
                                (is_real_dense(rep) ? 2 : 1) * (prec == HRD_F64 ? 1 : prec == HRD_F32 ? 2 : 4))
                : (is_su2_row(rep) ? 4 : rep == HRD_FUND ? 8 : 9) * (prec == HRD_F64 ? 8 : prec == HRD_F32 ? 4 : 2);
@@ -987,6 +988,111 @@ struct RealIO {
                 for (int j = 0; j < 8; j++) v[j] = to_h16(e[j]);
                 st16h<false>(a, v);
             }
+        }
+    }
+};
+
+// SU(3) links stored as their first two rows (6 complex entries, row-major);
+// the third row is the complex conjugate of the cross product of the first
+// two (exact for SU(3): det U = 1 and U unitary).  Planes: F64 six complex128,
+// F32 three of 2 x complex64, F16 one 16-byte plane (entries 0-3) and one
+// 8-byte plane (entries 4, 5).
+template <typename S>
+struct LinkIO<HRD_SU3_ROW2, S> {
+    using A = typename Arith<S>::type;
+    using Link = CLink<3, A>;
+    static constexpr size_t kBytes = std::is_same<S, double>::value ? 96 : std::is_same<S, float>::value ? 48 : 24;
+    template <bool NT = false>
+    __device__ __forceinline__ static void load_rows01(const void *U, int Vh, int p, int mu, int site, Cx<A> (&e)[6])
+    {
+        const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kBytes;
+        if constexpr (std::is_same<S, double>::value) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const vd2 v = ld16d<NT>(b + ((size_t)k * Vh + site) * 16);
+                e[k] = Cx<A>{v.x, v.y};
+            }
+        } else if constexpr (std::is_same<S, float>::value) {
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
+                e[2 * q] = Cx<A>{v.x, v.y};
+                e[2 * q + 1] = Cx<A>{v.z, v.w};
+            }
+        } else {
+            const vh8 v = ld16h<NT>(b + (size_t)site * 16);
+            const vh4 w = ld8h<NT>(b + (size_t)Vh * 16 + (size_t)site * 8);
+#pragma unroll
+            for (int k = 0; k < 4; k++) e[k] = Cx<A>{(float)v[2 * k], (float)v[2 * k + 1]};
+            e[4] = Cx<A>{(float)w[0], (float)w[1]};
+            e[5] = Cx<A>{(float)w[2], (float)w[3]};
+        }
+    }
+    // row 2 = conj(row 0 x row 1)
+    __device__ __forceinline__ static void third_row(const Cx<A> (&e)[6], Cx<A> (&r)[3])
+    {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int i = (k + 1) % 3, j = (k + 2) % 3;
+            const Cx<A> z = cmul(e[i], e[3 + j]) - cmul(e[j], e[3 + i]);
+            r[k] = Cx<A>{z.re, -z.im};
+        }
+    }
+    template <int I, bool NT = false>
+    __device__ __forceinline__ static void load_row(const void *U, int Vh, int p, int mu, int site, Cx<A> (&row)[3])
+    {
+        Cx<A> e[6];
+        load_rows01<NT>(U, Vh, p, mu, site, e);
+        if constexpr (I < 2) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) row[k] = e[3 * I + k];
+        } else {
+            third_row(e, row);
+        }
+    }
+    template <bool NT = false>
+    __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
+    {
+        Cx<A> e[6];
+        load_rows01<NT>(U, Vh, p, mu, site, e);
+        Link l;
+#pragma unroll
+        for (int k = 0; k < 6; k++) l.u[k / 3][k % 3] = e[k];
+        Cx<A> r[3];
+        third_row(e, r);
+#pragma unroll
+        for (int k = 0; k < 3; k++) l.u[2][k] = r[k];
+        return l;
+    }
+    template <typename T>
+    __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const CLink<3, T> &l)
+    {
+        char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kBytes;
+        Cx<T> e[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) e[k] = l.u[k / 3][k % 3];
+        if constexpr (std::is_same<S, double>::value) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) st16d<false>(b + ((size_t)k * Vh + site) * 16, vd2{(double)e[k].re, (double)e[k].im});
+        } else if constexpr (std::is_same<S, float>::value) {
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+                st16f<false>(b + ((size_t)q * Vh + site) * 16, vf4{(float)e[2 * q].re, (float)e[2 * q].im,
+                                                                    (float)e[2 * q + 1].re, (float)e[2 * q + 1].im});
+        } else {
+            vh8 v;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                v[2 * k] = to_h16(e[k].re);
+                v[2 * k + 1] = to_h16(e[k].im);
+            }
+            st16h<false>(b + (size_t)site * 16, v);
+            vh4 w;
+            w[0] = to_h16(e[4].re);
+            w[1] = to_h16(e[4].im);
+            w[2] = to_h16(e[5].re);
+            w[3] = to_h16(e[5].im);
+            *reinterpret_cast<vh4 *>(b + (size_t)Vh * 16 + (size_t)site * 8) = w;
         }
     }
 };

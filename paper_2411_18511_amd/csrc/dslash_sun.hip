@@ -1,6 +1,6 @@
 // Wilson hopping stencil for the dense SU(N > 2) link formats (CPLX3, CPLX4,
-// CPLX6, REAL8): the same kernel template as the SU(2) formats with N x N
-// colour products; no clover epilogues.
+// CPLX6, REAL8, SU3_ROW2): the same kernel template as the SU(2) formats with
+// N x N colour products; no clover epilogues.
 #include "hop.h"
 
 namespace hrd {
@@ -14,6 +14,7 @@ hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool n
         case HRD_CPLX3: return dispatch_hop<HRD_CPLX3, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
         case HRD_CPLX4: return dispatch_hop<HRD_CPLX4, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
         case HRD_CPLX6: return dispatch_hop<HRD_CPLX6, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
+        case HRD_SU3_ROW2: return dispatch_hop<HRD_SU3_ROW2, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
         default: return dispatch_hop<HRD_REAL8, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
     }
 }
@@ -25,6 +26,7 @@ hipError_t dense_rupd_for(int rep, const HopArgs &a, hipStream_t st)
         case HRD_CPLX3: return dispatch_rupd<HRD_CPLX3, S>(a, st, CLOV_NONE);
         case HRD_CPLX4: return dispatch_rupd<HRD_CPLX4, S>(a, st, CLOV_NONE);
         case HRD_CPLX6: return dispatch_rupd<HRD_CPLX6, S>(a, st, CLOV_NONE);
+        case HRD_SU3_ROW2: return dispatch_rupd<HRD_SU3_ROW2, S>(a, st, CLOV_NONE);
         default: return dispatch_rupd<HRD_REAL8, S>(a, st, CLOV_NONE);
     }
 }

@@ -7,7 +7,8 @@
 // components:  sum_s A_s (x) ((1+SIG g)B)_s^* = sum_{t=0,1} h(A)_t (x) h(B)_t^*
 // with h the upper half of (1 + SIG g_mu) applied to the field.
 // One thread per site computes the four links leaving it; every output link
-// has exactly one writer (no atomics).
+// has exactly one writer (no atomics).  For the dense SU(N > 2) formats the
+// derivative is written in the format itself (real part only for REAL8).
 #include "kernels.h"
 #include "spin.h"
 
@@ -38,32 +39,57 @@ __device__ __forceinline__ void force_dir(const Geom &g, const Site &s, int idx,
     project<MU, +1, N, double>(Xf, d0, d1);
     const double sg = (MU == 0 && s.x[0] == g.L[0] - 1) ? -1.0 : 1.0;
     const double w = -0.5 * sg * scale;
-    Cx<double> G[N][N];
+    // G_ik = w (a_i conj(b_k) + a'_i conj(b'_k) + c_i conj(d_k) + c'_i conj(d'_k))
+    auto entry = [&](int i, int k) {
+        Cx<double> z = cmulc(b0[k], a0[i]);
+        z = cfmac(b1[k], a1[i], z);
+        z = cfmac(d0[k], c0[i], z);
+        z = cfmac(d1[k], c1[i], z);
+        return Cx<double>{w * z.re, w * z.im};
+    };
+    if constexpr (is_dense(REP)) {
+        // dense formats, FP64 layout: entry e = N i + k in plane e (CPLXn:
+        // one complex per plane; REAL8: two reals per plane), rows stored
+        // as they are formed
+        char *blk = reinterpret_cast<char *>(F) +
+                    (size_t)(4 * p + MU) * g.Vh * (size_t)link_bytes(REP, HRD_F64);
 #pragma unroll
-    for (int i = 0; i < N; i++)
+        for (int i = 0; i < N; i++) {
+            if constexpr (is_real_dense(REP)) {
 #pragma unroll
-        for (int k = 0; k < N; k++) {
-            // a_i conj(b_k) + ...
-            Cx<double> z = cmulc(b0[k], a0[i]);
-            z = cfmac(b1[k], a1[i], z);
-            z = cfmac(d0[k], c0[i], z);
-            z = cfmac(d1[k], c1[i], z);
-            G[i][k] = Cx<double>{w * z.re, w * z.im};
+                for (int k = 0; k < N; k += 2) {
+                    const int q = (N * i + k) / 2;
+                    st16d<false>(blk + ((size_t)q * g.Vh + idx) * 16, vd2{entry(i, k).re, entry(i, k + 1).re});
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < N; k++) {
+                    const Cx<double> z = entry(i, k);
+                    st16d<false>(blk + ((size_t)(N * i + k) * g.Vh + idx) * 16, vd2{z.re, z.im});
+                }
+            }
         }
-    if constexpr (REP == HRD_FUND) {
-        FundLink<double> l;
-#pragma unroll
-        for (int i = 0; i < 2; i++)
-#pragma unroll
-            for (int k = 0; k < 2; k++) l.u[i][k] = G[i][k];
-        LinkIO<HRD_FUND, double>::store(F, g.Vh, p, MU, idx, l);
     } else {
-        AdjLink<double> l;
+        Cx<double> G[N][N];
 #pragma unroll
-        for (int i = 0; i < 3; i++)
+        for (int i = 0; i < N; i++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) l.r[i][k] = G[i][k].re;
-        LinkIO<HRD_ADJ, double>::store(F, g.Vh, p, MU, idx, l);
+            for (int k = 0; k < N; k++) G[i][k] = entry(i, k);
+        if constexpr (base_rep(REP) == HRD_FUND) {
+            FundLink<double> l;
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int k = 0; k < 2; k++) l.u[i][k] = G[i][k];
+            LinkIO<HRD_FUND, double>::store(F, g.Vh, p, MU, idx, l);
+        } else {
+            AdjLink<double> l;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) l.r[i][k] = G[i][k].re;
+            LinkIO<HRD_ADJ, double>::store(F, g.Vh, p, MU, idx, l);
+        }
     }
 }
 
@@ -96,8 +122,14 @@ hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, vo
     const dim3 grid(2 * ((g.Vh + kBlock - 1) / kBlock)), block(kBlock);
     const char *x = reinterpret_cast<const char *>(X);
     const char *y = reinterpret_cast<const char *>(Y);
-    if (base_rep(rep) == HRD_FUND) hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale);
-    else hipLaunchKernelGGL(force_kernel<HRD_ADJ>, grid, block, 0, st, g, x, y, F, scale);
+    switch (base_rep(rep)) {
+        case HRD_FUND: hipLaunchKernelGGL(force_kernel<HRD_FUND>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_ADJ: hipLaunchKernelGGL(force_kernel<HRD_ADJ>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_CPLX3: hipLaunchKernelGGL(force_kernel<HRD_CPLX3>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_CPLX4: hipLaunchKernelGGL(force_kernel<HRD_CPLX4>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_CPLX6: hipLaunchKernelGGL(force_kernel<HRD_CPLX6>, grid, block, 0, st, g, x, y, F, scale); break;
+        default: hipLaunchKernelGGL(force_kernel<HRD_REAL8>, grid, block, 0, st, g, x, y, F, scale); break;
+    }
     return hipGetLastError();
 }
 

@@ -209,6 +209,7 @@ void pack_dense_for(int rep, const Geom &g, void *nat, void *packed, bool unpack
         case HRD_CPLX3: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX3, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         case HRD_CPLX4: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX4, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         case HRD_CPLX6: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX6, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
+        case HRD_SU3_ROW2: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_SU3_ROW2, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         default: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_REAL8, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
     }
 }
@@ -221,6 +222,7 @@ void convert_dense_for(int rep, const Geom &g, const void *U64, void *Uout, hipS
         case HRD_CPLX3: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX3, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         case HRD_CPLX4: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX4, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         case HRD_CPLX6: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX6, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
+        case HRD_SU3_ROW2: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_SU3_ROW2, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         default: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_REAL8, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
     }
 }

@@ -28,7 +28,7 @@ _lib = ctypes.CDLL(LIBPATH)
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
 FUND, ADJ, FUND_SU2, ADJ_SU2 = 0, 1, 2, 3
-CPLX3, CPLX4, CPLX6, REAL8 = 4, 5, 6, 7
+CPLX3, CPLX4, CPLX6, REAL8, SU3_ROW2 = 4, 5, 6, 7, 8
 SUN_FUND, SUN_ADJ, SUN_SYM, SUN_ASYM = 0, 1, 2, 3
 F64, F32, F16 = 0, 1, 2
 FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
@@ -41,9 +41,9 @@ _REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, "fund_su
          "adj_su2": ADJ_SU2, "cplx3": CPLX3, "cplx4": CPLX4, "cplx6": CPLX6, "real8": REAL8,
          # SU(N > 2) representations by name -> their link formats
          "su3_fund": CPLX3, "su3_asym": CPLX3, "su3_sym": CPLX6, "su3_adj": REAL8, "su4_fund": CPLX4,
-         "su4_asym": CPLX6,
+         "su4_asym": CPLX6, "su3_row2": SU3_ROW2,
          FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2, CPLX3: CPLX3, CPLX4: CPLX4, CPLX6: CPLX6,
-         REAL8: REAL8}
+         REAL8: REAL8, SU3_ROW2: SU3_ROW2}
 _SUN_KINDS = {"fund": SUN_FUND, "adj": SUN_ADJ, "sym": SUN_SYM, "asym": SUN_ASYM}
 _PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "f16": F16, "fp16": F16, F64: F64, F32: F32,
           F16: F16, torch.float64: F64, torch.float32: F32}
@@ -210,12 +210,14 @@ class Geometry:
 
 def ncolour(rep):
     """Colours of the fermion in a link format (2, 3, 4, 6 or 8)."""
-    return {FUND: 2, FUND_SU2: 2, ADJ: 3, ADJ_SU2: 3, CPLX3: 3, CPLX4: 4, CPLX6: 6, REAL8: 8}[_REPS[rep]]
+    return {FUND: 2, FUND_SU2: 2, ADJ: 3, ADJ_SU2: 3, CPLX3: 3, CPLX4: 4, CPLX6: 6, REAL8: 8, SU3_ROW2: 3}[_REPS[rep]]
 
 
 def base_rep(rep):
     """Uncompressed representation whose gauge layout derivatives use."""
     r = _REPS[rep]
+    if r == SU3_ROW2:
+        return CPLX3
     if r >= CPLX3:
         return r
     return FUND if ncolour(r) == 2 else ADJ

@@ -10,13 +10,17 @@ CPLX4, CPLX6 and REAL8.
   per-component / norm-wise bounds of the 16-bit format (oracle on the
   F16-rounded links and spinors);
 * FP64, mixed and MIXED16 CG reach a true residual <= 1e-10 (oracle
-  recomputation).
+  recomputation);
+* the force d/dU Re<X, D[U] Y> and the action force with respect to the
+  representation's links equal the oracle's to 1e-13 (real part for the
+  real adjoint links).
 """
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import FieldSUN, requires_gpu, rel_err, hrd, to_dev_gauge
+from paper_2411_18511_amd import inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -125,16 +129,74 @@ def test_cg_sun(oracle, nc, rep, mode):
     assert oracle.true_residual(F.U_orc, b_np, xg, m0) <= 1e-10
 
 
+@pytest.mark.parametrize("nc,rep", CASES)
+def test_force_sun(oracle, nc, rep):
+    h = hrd()
+    dims, m0 = (4, 2, 4, 6), -0.3
+    F = FieldSUN(dims, nc, rep, seed=41)
+    real = F.fmt == h.REAL8
+    V = int(np.prod(dims))
+
+    def unpack_force(Fp):
+        G = h.unpack_gauge(Fp, dims, F.fmt, "f64").cpu().numpy()
+        return G.reshape((4,) + dims + (F.n, F.n))
+
+    X, Y = F.spinor(42), F.spinor(43)
+    got = unpack_force(h.dirac_force(F.U64, F.pack(X), F.pack(Y), dims, F.fmt, scale=0.7))
+    want = 0.7 * oracle.force(X, Y, real_links=real)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    xi = oracle.restrict(F.spinor(44), 0)
+    got = unpack_force(h.action_force(F.U64, F.pack(xi, "f64", "even"), m0, dims, F.fmt, scale=1.5))
+    Xa, Ya = oracle.action_force_fields(F.U_orc, xi, m0)
+    want = 1.5 * (2.0 / (4 + m0)) * oracle.force(Xa, Ya, real_links=real)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
 def test_sun_errors():
     h = hrd()
     dims = (4, 4, 4, 4)
     assert h.sun_rep_format(4, "sym") is None and h.sun_rep_format(5, "fund") is None
     F = FieldSUN(dims, 3, "sym", seed=31)
-    psi = F.pack(F.spinor(32), "f64", "all")
-    # the force, clover and batched paths take the SU(2) formats only
-    with pytest.raises(h.HrdError) as e:
-        h.dirac_force(F.U64, psi, psi, dims, F.fmt)
-    assert e.value.status == h.EINVAL
+    # the clover and batched paths take the SU(2) formats only
     with pytest.raises(h.HrdError) as e:
         h.clover_build(F.U64, 1.0, -0.2, dims, F.fmt)
     assert e.value.status == h.EINVAL
+
+
+@pytest.mark.parametrize("dims", LATS)
+def test_su3_two_row_format(oracle, dims):
+    """SU(3) fundamental links stored as two rows: unpack reconstructs the third
+    row, and the operator, CG and force equal those of the full links."""
+    h = hrd()
+    m0 = -0.3
+    Uf = inputs.gauge_field_sun(dims, 51, 3)
+    nat = to_dev_gauge(Uf)
+    U64 = h.pack_gauge(nat, dims, "su3_row2", "f64")
+    assert U64.numel() == int(np.prod(dims)) * 4 * 96
+    back = h.unpack_gauge(U64, dims, "su3_row2", "f64").cpu().numpy().reshape(Uf.shape)
+    assert np.abs(back - Uf).max() < 1e-14
+    psi = inputs.gaussian_spinor(dims, 3, 52)
+    pe = oracle.restrict(psi, 0)
+    want = oracle.dhat(Uf, pe, m0)
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        Ug = U64 if prec == "f64" else h.convert_gauge_prec(U64, dims, "su3_row2", prec)
+        src = h.pack_spinor(torch.from_numpy(pe.reshape(-1, 4, 3)).cuda(), dims, "su3_row2", prec, "even")
+        out = h.dirac_apply(Ug, src, m0, "su3_row2", "eo", dims, prec=prec)
+        got = h.unpack_spinor(out, dims, "su3_row2", prec, "even").cpu().numpy().reshape(psi.shape)
+        assert rel_err(got, want) <= tol, prec
+        full = h.dirac_apply(Ug, h.pack_spinor(torch.from_numpy(psi.reshape(-1, 4, 3)).cuda(), dims, "su3_row2",
+                                               prec, "all"), m0, "su3_row2", "full", dims, prec=prec, dagger=True)
+        got = h.unpack_spinor(full, dims, "su3_row2", prec, "all").cpu().numpy().reshape(psi.shape)
+        assert rel_err(got, oracle.dirac_dagger(Uf, psi, m0)) <= tol, prec
+    b = h.pack_spinor(torch.from_numpy(pe.reshape(-1, 4, 3)).cuda(), dims, "su3_row2", "f64", "even")
+    U16 = h.convert_gauge_prec(U64, dims, "su3_row2", "f16")
+    x, info = h.cg_solve(U64, b, m0, 1e-10, dims, "su3_row2", mode="mixed16", U32=U16)
+    xg = h.unpack_spinor(x, dims, "su3_row2", "f64", "even").cpu().numpy().reshape(psi.shape)
+    assert info["true_rel_residual"] <= 1e-10 and oracle.true_residual(Uf, pe, xg, m0) <= 1e-10
+    # the force is a general 3 x 3 matrix: written in the CPLX3 layout
+    X, Y = inputs.gaussian_spinor(dims, 3, 53), inputs.gaussian_spinor(dims, 3, 54)
+    Xp = h.pack_spinor(torch.from_numpy(X.reshape(-1, 4, 3)).cuda(), dims, "su3_row2", "f64", "all")
+    Yp = h.pack_spinor(torch.from_numpy(Y.reshape(-1, 4, 3)).cuda(), dims, "su3_row2", "f64", "all")
+    G = h.unpack_gauge(h.dirac_force(U64, Xp, Yp, dims, "su3_row2"), dims, "cplx3", "f64").cpu().numpy()
+    wantG = oracle.force(X, Y)
+    assert np.abs(G.reshape(wantG.shape) - wantG).max() <= 1e-13 * np.abs(wantG).max()
