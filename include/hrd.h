@@ -463,8 +463,9 @@ hrd_status hrd_cg_solve_clover(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode 
                                      + ((1 + g_mu) Y(x)) (x) X(x+mu)^* ],
    (a (x) b^*)_ij = a_i conj(b_j).  X and Y are packed full-lattice FP64
    spinors; F is a packed FP64 gauge-layout field of the uncompressed
-   representation (FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2),
-   because a derivative is a general matrix.  For ADJ the links are real and
+   representation (FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2, the
+   format itself for CPLXn and REAL8, CPLX3 for SU3_ROW2), because a
+   derivative is a general matrix.  For ADJ and REAL8 the links are real and
    F = scale * Re G.  D is linear in U, so G does not depend on U;
    U is accepted so the call mirrors the operator's arguments and may be NULL.
    Asynchronous. */
