@@ -169,7 +169,7 @@ hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const voi
                       bool dag, hipStream_t st, const CloverRef *cl)
 {
     HopArgs a{};
-    a.g = g;
+    a.g = make_geom(g.L, choose_slab_full(g.L, prec));
     a.U = U;
     a.src = (const char *)in;
     a.dst = (char *)out;

@@ -25,6 +25,13 @@
 #include "api_util.h"
 #include "spin.h"
 
+// 1: each thread holds its site's 8 links in registers across the group of
+// right-hand sides; 0: the links are re-read (from L2 after the first) for
+// each right-hand side, which leaves the registers for more loads in flight.
+#ifndef HRD_BLINKS_REGS
+#define HRD_BLINKS_REGS 1
+#endif
+
 namespace hrd {
 
 namespace {
@@ -122,8 +129,10 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
         for (int mu = 0; mu < 4; mu++) {
             jf[mu] = nbr_fwd(g, s, mu);
             jb[mu] = nbr_bwd(g, s, mu);
-            lf[mu] = LIO::template load<true>(d.U32, g.Vh, parity, mu, idx);
-            lb[mu] = LIO::template load<true>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
+            if constexpr (HRD_BLINKS_REGS) {
+                lf[mu] = LIO::template load<true>(d.U32, g.Vh, parity, mu, idx);
+                lb[mu] = LIO::template load<true>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
+            }
         }
         nf = s.x[0] == g.L[0] - 1;
         nb = s.x[0] == 0;
@@ -135,6 +144,13 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
         if (mode && mode[d.rhs_base + rhs] == M_DONE) continue;  // uniform
         double nrm = 0;
         if (in) {
+            if constexpr (!HRD_BLINKS_REGS) {
+#pragma unroll
+                for (int mu = 0; mu < 4; mu++) {
+                    lf[mu] = LIO::template load<false>(d.U32, g.Vh, parity, mu, idx);
+                    lb[mu] = LIO::template load<false>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
+                }
+            }
             const char *src = d.buf[src_id] + (size_t)rhs * d.fbytes;
             Cx<float> acc[NC];
 #pragma unroll

@@ -64,6 +64,8 @@ struct Geom {
 // in t inside x1-slabs of width B, so the t-neighbour rows of a sweep are
 // B rows apart and stay in the XCD's L2.  B = L1 is plain lexicographic order.
 int choose_slab(const int dims[4]);
+// Slab width of the one-launch plain operator (both parities), per precision.
+int choose_slab_full(const int dims[4], int prec);
 
 inline Geom make_geom(const int dims[4], int slab = 0)
 {

@@ -19,6 +19,21 @@ int choose_slab(const int dims[4])
     return best;
 }
 
+// Slab of the FULL kernel (both parities in one launch, temporal link loads):
+// its t-window holds the links shared by the two parities as well, so the
+// FP64 budget is half the single-parity one (measured at 48^4: FP64 plain D
+// 821 -> 742 us with slab 3 instead of 6; FP32 best at the default slab).
+int choose_slab_full(const int dims[4], int prec)
+{
+    if (HRD_SLAB > 0 && dims[1] % HRD_SLAB == 0) return HRD_SLAB;
+    const long budget = prec == HRD_F64 ? 3456 : 6912;
+    const long R = (long)dims[2] * dims[3] / 2;
+    int best = 1;
+    for (int b = 1; b <= dims[1]; b++)
+        if (dims[1] % b == 0 && (long)b * R <= budget) best = b;
+    return best;
+}
+
 namespace {
 
 template <typename S>

@@ -24,6 +24,12 @@
 // MI355X; see the design notes): non-temporal link loads and output stores,
 // minimum waves per SIMD, and the x1-slab width of the traversal (0: chosen
 // per lattice by choose_slab).
+// Non-temporal link loads in the FULL (both parities in one launch) kernel:
+// there every link is used by one even and one odd target, and the blocks of
+// the two parities at the same position run side by side on one XCD.
+#ifndef HRD_NT_LINKS_FULL
+#define HRD_NT_LINKS_FULL 0
+#endif
 #ifndef HRD_NT_LINKS
 #define HRD_NT_LINKS 1
 #endif
@@ -66,7 +72,7 @@ __device__ __forceinline__ void dir_fence(Cx<R> (&acc)[NC])
 }
 
 // S: storage type of the source spinor and the links; R: arithmetic type.
-template <int MU, bool DAG, int REP, typename S, typename R = typename Arith<S>::type>
+template <int MU, bool DAG, int REP, typename S, bool NTL = HRD_NT_LINKS, typename R = typename Arith<S>::type>
 __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, int p, const void *U,
                                         const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
 {
@@ -80,7 +86,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         const int j = nbr_fwd(g, s, MU);
         Cx<R> psi[NC];
         IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::template load<HRD_NT_LINKS>(U, g.Vh, p, MU, idx);
+        const auto l = LIO::template load<NTL>(U, g.Vh, p, MU, idx);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SF, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == g.L[0] - 1) {
@@ -99,7 +105,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         const int j = nbr_bwd(g, s, MU);
         Cx<R> psi[NC];
         IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::template load<HRD_NT_LINKS>(U, g.Vh, 1 - p, MU, j);
+        const auto l = LIO::template load<NTL>(U, g.Vh, 1 - p, MU, j);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SB, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == 0) {
@@ -290,13 +296,14 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             hop_dir_dense<2, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
             hop_dir_dense<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         } else {
-            hop_dir<0, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            constexpr bool NTL = FULL ? HRD_NT_LINKS_FULL : HRD_NT_LINKS;
+            hop_dir<0, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
             if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
-            hop_dir<1, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            hop_dir<1, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
             if constexpr (HRD_FENCE >= 1) dir_fence(acc);
-            hop_dir<2, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            hop_dir<2, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
             if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
-            hop_dir<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
+            hop_dir<3, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
         }
         const R cb = (R)a.b;
         Cx<R> out[NC];
