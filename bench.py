@@ -203,7 +203,8 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
     and adjoint (REAL8) representations: representation build, hopping block
     in FP64 / FP32 / F16 and even/odd D^ in FP32 (algorithmic bytes on
     unpadded links), and mixed / MIXED16 CG to 1e-10 for the fundamental; the
-    fundamental also in the two-row format."""
+    fundamental also in the two-row format, with the clover-improved D^ (FP32)
+    and MIXED16 clover CG."""
     V = int(np.prod(dims))
     Uf = inputs.gauge_field_sun(dims, 7, 3, kind="product")
     Uf_dev = torch.from_numpy(Uf.reshape(4, V, 3, 3)).to(dev)
@@ -277,6 +278,32 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
             b.record()
             b.synchronize()
             r["cg_f64"] = {"ms": a.elapsed_time(b), **info}
+        if rep == "fund_row2":
+            # clover-improved SU(3) operator (c_sw = 1): D^_sw in FP32, MIXED16 CG
+            c64 = hrd.clover_build(U64, 1.0, m0, dims, fmt)
+            c32 = hrd.convert_clover(c64, dims, fmt)
+            U32 = hrd.convert_gauge_prec(U64, dims, fmt, "f32")
+            U16 = hrd.convert_gauge_prec(U64, dims, fmt, "f16")
+            se = hrd.convert_spinor_prec(src_e, dims, fmt, 1, "f64", "f32")
+            dst = torch.empty_like(se)
+            op = hrd.CloverOp(U32, c32, dims, fmt, "eo")
+            op(se, dst)
+            a.record()
+            for _ in range(reps // 2):
+                op(se, dst)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b) / (reps // 2)
+            L, S, C = SUN_LINK_BYTES[name] // 2, 32 * n, 8 * n * n * 4
+            alg = V * 8 * L + (V // 2) * 5 * S + V * C
+            r["clover_dhat_f32"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
+                                    "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            a.record()
+            _, info = hrd.cg_solve_clover(U64, c64, src_e, tol, dims, fmt, mode="mixed16", U32=U16, clov32=c32)
+            b.record()
+            b.synchronize()
+            r["clover_cg_mixed16"] = {"ms": a.elapsed_time(b), **info}
+            del c64, c32, U32, U16, se, dst, op
         out[rep] = r
         del U64, src_o, src_e
     return out

@@ -47,9 +47,11 @@ hrd_status check_lattice(const hrd_lattice *lat)
     return HRD_OK;
 }
 
-hrd_status check_su2_format(hrd_rep rep, const char *what)
+hrd_status check_clover_format(hrd_rep rep, const char *what)
 {
-    if (is_dense(rep)) return fail(HRD_EINVAL, "%s supports the SU(2) link formats only (rep %d)", what, (int)rep);
+    if (!clover_capable(rep))
+        return fail(HRD_EINVAL, "%s supports the SU(2) formats and SU(3) fundamental links only (rep %d)", what,
+                    (int)rep);
     return HRD_OK;
 }
 
@@ -470,7 +472,7 @@ hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
 
 size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
 {
-    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK || is_dense(rep)) return 0;
+    if (check_lattice(lat) != HRD_OK || check_rep_prec(rep, prec) != HRD_OK || !clover_capable(rep)) return 0;
     return clover_bytes(lat, rep, prec);
 }
 
@@ -478,7 +480,7 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind
                             double m0, void *M64, void *Minv64, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_clover_build"));
+    HRD_TRY(check_clover_format(rep, "hrd_clover_build"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (kind != HRD_CLOVER_SW && kind != HRD_CLOVER_EXP) return fail(HRD_EINVAL, "invalid clover kind %d", (int)kind);
     if (!U64 || !M64 || !Minv64) return fail(HRD_EINVAL, "NULL field pointer");
@@ -497,7 +499,7 @@ hrd_status hrd_clover_build(const hrd_lattice *lat, hrd_rep rep, hrd_clover_kind
 hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C32, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_convert_clover"));
+    HRD_TRY(check_clover_format(rep, "hrd_convert_clover"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!C64 || !C32) return fail(HRD_EINVAL, "NULL field pointer");
     if (overlap(C64, clover_bytes(lat, rep, HRD_F64), C32, clover_bytes(lat, rep, HRD_F32)))
@@ -509,7 +511,7 @@ hrd_status hrd_convert_clover(const hrd_lattice *lat, hrd_rep rep, const void *C
 hrd_status hrd_unpack_clover(const hrd_lattice *lat, hrd_rep rep, const void *C64, void *C_nat, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_unpack_clover"));
+    HRD_TRY(check_clover_format(rep, "hrd_unpack_clover"));
     HRD_TRY(check_rep_prec(rep, HRD_F64));
     if (!C64 || !C_nat) return fail(HRD_EINVAL, "NULL field pointer");
     const size_t cb = clover_bytes(lat, rep, HRD_F64);
@@ -523,7 +525,7 @@ hrd_status hrd_dirac_apply_clover(const hrd_lattice *lat, hrd_rep rep, hrd_prec 
                                   void *work, void *stream)
 {
     HRD_TRY(check_lattice(lat));
-    HRD_TRY(check_su2_format(rep, "hrd_dirac_apply_clover"));
+    HRD_TRY(check_clover_format(rep, "hrd_dirac_apply_clover"));
     HRD_TRY(check_rep_prec_any(rep, prec));
     if (parity != HRD_FULL && parity != HRD_EO)
         return fail(HRD_EINVAL, "clover operator supports HRD_FULL and HRD_EO (hop blocks are those of hrd_dirac_apply)");
@@ -655,7 +657,7 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     if (mode != HRD_CG_F64 && !U32)
         return finish(fail(HRD_EINVAL, "mixed CG needs the reduced-precision gauge field (FP32 or F16)"));
     if (!cl64 && (!std::isfinite(m0) || 4.0 + m0 == 0.0)) return finish(fail(HRD_EINVAL, "invalid m0 %g", m0));
-    if (cl64 && is_dense(rep)) return finish(check_su2_format(rep, "hrd_cg_solve_clover"));
+    if (cl64 && !clover_capable(rep)) return finish(check_clover_format(rep, "hrd_cg_solve_clover"));
     if (cl64 && (!cl64->M || !cl64->Minv)) return finish(fail(HRD_EINVAL, "NULL FP64 clover field"));
     if (cl64 && mode != HRD_CG_F64 && (!cl32 || !cl32->M || !cl32->Minv))
         return finish(fail(HRD_EINVAL, "mixed CG needs the FP32 clover fields"));

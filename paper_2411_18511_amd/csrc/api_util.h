@@ -19,7 +19,7 @@ hrd_status check_hip(hipError_t e, const char *what);
 hrd_status check_lattice(const hrd_lattice *lat);
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec);      // F64 or F32
 hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec);  // F64, F32 or F16
-hrd_status check_su2_format(hrd_rep rep, const char *what);   // EINVAL for the dense SU(N) formats
+hrd_status check_clover_format(hrd_rep rep, const char *what);  // EINVAL unless clover_capable(rep)
 bool overlap(const void *a, size_t na, const void *b, size_t nb);
 size_t spinor_bytes(const hrd_lattice *lat, int rep, int prec, int nparity);
 size_t gauge_bytes(const hrd_lattice *lat, int rep, int prec);

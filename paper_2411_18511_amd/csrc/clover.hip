@@ -1,5 +1,6 @@
 // Clover term of the improved Wilson operator (the paper's Sec. 2.2: an
-// extra site-diagonal term whose derived fields are precomputed once per
+// extra site-diagonal term, for the SU(2) formats and SU(3) fundamental links
+// (CPLX3, SU3_ROW2), whose derived fields are precomputed once per
 // gauge field).  One thread per site builds
 //   M(x) = m + A(x),  A(x) = c_sw (i/4) sum_{mu,nu} sigma_{mu nu} F_{mu nu}(x),
 // with F the four-leaf field strength (Q - Q^+)/8, and its inverse, which the
@@ -63,6 +64,17 @@ __device__ __forceinline__ CMat<2> as_mat(const FundLink<double> &l)
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) c.m[i][j] = l.u[i][j];
+    return c;
+}
+
+template <int N>
+__device__ __forceinline__ CMat<N> as_mat(const CLink<N, double> &l)
+{
+    CMat<N> c;
+#pragma unroll
+    for (int i = 0; i < N; i++)
+#pragma unroll
+        for (int j = 0; j < N; j++) c.m[i][j] = l.u[i][j];
     return c;
 }
 
@@ -395,6 +407,12 @@ hipError_t launch_build(int rep, const Geom &g, const void *U, double csw, doubl
             break;
         case HRD_FUND_SU2:
             hipLaunchKernelGGL((clover_build_kernel<HRD_FUND_SU2, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
+            break;
+        case HRD_CPLX3:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_CPLX3, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
+            break;
+        case HRD_SU3_ROW2:
+            hipLaunchKernelGGL((clover_build_kernel<HRD_SU3_ROW2, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);
             break;
         default:
             hipLaunchKernelGGL((clover_build_kernel<HRD_ADJ_SU2, EXP>), grid, block, 0, st, g, U, csw, m, Mf, Mi);

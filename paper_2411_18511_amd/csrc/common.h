@@ -431,6 +431,11 @@ __host__ __device__ constexpr int ncolour(int rep)
 // Dense link formats of SU(N > 2) representations.
 __host__ __device__ constexpr bool is_dense(int rep) { return rep >= HRD_CPLX3; }
 __host__ __device__ constexpr bool is_real_dense(int rep) { return rep == HRD_REAL8; }
+// Formats the clover term supports: the SU(2) ones and SU(3) fundamental links.
+__host__ __device__ constexpr bool clover_capable(int rep)
+{
+    return !is_dense(rep) || rep == HRD_CPLX3 || rep == HRD_SU3_ROW2;
+}
 
 // Representation whose (uncompressed) layout a derivative with respect to the
 // links uses: FUND for FUND and FUND_SU2, ADJ for ADJ and ADJ_SU2, the format

@@ -64,7 +64,7 @@ int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov)
 {
-    if (is_dense(rep)) return launch_hop_rupdate_dense(rep, prec, a, st);
+    if (is_dense(rep)) return launch_hop_rupdate_dense(rep, prec, a, st, clov);
     switch (prec) {
         case HRD_F64: return rupd_for<double>(rep, a, st, clov);
         case HRD_F32: return rupd_for<float>(rep, a, st, clov);
@@ -75,7 +75,7 @@ hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t s
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st, int clov)
 {
-    if (is_dense(rep)) return launch_hop_dense(rep, prec, a, dag, has_a, norm, full, st);
+    if (is_dense(rep)) return launch_hop_dense(rep, prec, a, dag, has_a, norm, full, st, clov);
     switch (prec) {
         case HRD_F64: return hop_for<double>(rep, a, dag, has_a, norm, full, st, clov);
         case HRD_F32: return hop_for<float>(rep, a, dag, has_a, norm, full, st, clov);

@@ -416,7 +416,7 @@ hipError_t dispatch_hop_clov(const HopArgs &a, bool dag, bool has_a, bool norm, 
 template <int REP, typename S>
 hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st, int clov)
 {
-    if constexpr (!is_dense(REP)) {
+    if constexpr (clover_capable(REP)) {
         if (clov == CLOV_SELF) {
             hipLaunchKernelGGL((hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>), dim3(hop_blocks(a.g)),
                                dim3(kHopBlock), 0, st, a);

@@ -35,10 +35,11 @@ hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a,
 // is not stored; instead r <- r - alpha out and ||r||^2 partials are written
 // (one per block, hop_blocks(g) of them).
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov = CLOV_NONE);
-// the same for the dense SU(N > 2) formats (no clover), dslash_sun.hip
+// the same for the dense SU(N > 2) formats (clover only for CPLX3 and
+// SU3_ROW2), dslash_sun.hip
 hipError_t launch_hop_dense(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
-                            hipStream_t st);
-hipError_t launch_hop_rupdate_dense(int rep, int prec, const HopArgs &a, hipStream_t st);
+                            hipStream_t st, int clov);
+hipError_t launch_hop_rupdate_dense(int rep, int prec, const HopArgs &a, hipStream_t st, int clov);
 
 // ----- field preparation (pack.hip) ----------------------------------------
 hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const void *nat, void *packed,

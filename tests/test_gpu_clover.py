@@ -20,7 +20,7 @@ from gpu_util import Field, requires_gpu, rel_err, hrd
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 REPS = ["fund", "adj", "fund_su2", "adj_su2"]
-LATS = [(4, 4, 4, 4), (6, 4, 6, 10), (4, 24, 48, 48)]
+LATS = [(4, 4, 4, 4), (6, 4, 6, 10), (4, 24, 48, 48), (2, 2, 2, 2), (4, 2, 2, 6)]
 
 
 @pytest.fixture(scope="module")
@@ -171,3 +171,48 @@ def test_clover_errors():
     with pytest.raises(h.HrdError) as e:
         h.clover_build(F.U64, float("nan"), -0.2, dims, "fund")
     assert e.value.status == h.EINVAL
+
+
+@pytest.mark.parametrize("fmt,kind", [(f, k) for f in ("cplx3", "su3_row2") for k in ("sw", "exp")])
+def test_clover_su3(oracle, fmt, kind):
+    """Clover-improved operator with SU(3) fundamental links (dense 3x3 and
+    two-row storage): site matrices, D_sw and D^_sw with daggers in FP64 and
+    FP32, and the FP64 / mixed / MIXED16 CG."""
+    from gpu_util import to_dev_gauge, to_dev_spinor, from_dev_spinor
+    from paper_2411_18511_amd import inputs
+
+    h = hrd()
+    m0, csw = -0.3, 1.4
+    for dims in ((4, 4, 4, 4), (6, 4, 6, 10), (2, 2, 2, 2)):
+        Uf = inputs.gauge_field_sun(dims, 61, 3, kind="smeared")
+        U64 = h.pack_gauge(to_dev_gauge(Uf), dims, fmt, "f64")
+        U32 = h.convert_gauge_prec(U64, dims, fmt, "f32")
+        U16 = h.convert_gauge_prec(U64, dims, fmt, "f16")
+        c64 = h.clover_build(U64, csw, m0, dims, fmt, kind=kind)
+        c32 = h.convert_clover(c64, dims, fmt)
+        M, Minv = oracle.clover_diag(Uf, m0, csw, kind)
+        gM = h.unpack_clover(c64.M, dims, fmt).cpu().numpy().reshape(M.shape)
+        assert np.abs(gM - M).max() <= 1e-13 * np.abs(M).max()
+        psi = inputs.gaussian_spinor(dims, 3, 62)
+        e = oracle.restrict(psi, 0)
+
+        def pack(x, prec, sites):
+            return h.pack_spinor(to_dev_spinor(x), dims, fmt, prec, sites)
+
+        def unpack(t, prec, sites):
+            return from_dev_spinor(h.unpack_spinor(t, dims, fmt, prec, sites), dims)
+
+        for dagger in (False, True):
+            wf = (oracle.dirac_clover_dagger if dagger else oracle.dirac_clover)(Uf, psi, m0, csw, kind)
+            we = (oracle.dhat_clover_dagger if dagger else oracle.dhat_clover)(Uf, e, m0, csw, (M, Minv))
+            for prec, Ug, cl, tol in (("f64", U64, c64, 1e-13), ("f32", U32, c32, 1e-6)):
+                out = h.dirac_apply_clover(Ug, cl, pack(psi, prec, "all"), fmt, "full", dims, dagger=dagger)
+                assert rel_err(unpack(out, prec, "all"), wf) <= tol, (dims, prec, "full", dagger)
+                out = h.dirac_apply_clover(Ug, cl, pack(e, prec, "even"), fmt, "eo", dims, dagger=dagger)
+                assert rel_err(unpack(out, prec, "even"), we) <= tol, (dims, prec, "eo", dagger)
+        b = pack(e, "f64", "even")
+        for mode, Ulo in (("f64", None), ("mixed", U32), ("mixed16", U16)):
+            x, info = h.cg_solve_clover(U64, c64, b, 1e-10, dims, fmt, mode=mode, U32=Ulo, clov32=c32)
+            assert info["true_rel_residual"] <= 1e-10
+            res = oracle.true_residual_clover(Uf, e, unpack(x, "f64", "even"), m0, csw, kind)
+            assert res <= 1e-10, (dims, mode, res)

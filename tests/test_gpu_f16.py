@@ -155,7 +155,7 @@ def _site_bound_check(got, want, n):
     return float((err / bound).max())
 
 
-@pytest.mark.parametrize("rep,dims", [(r, d) for r in REPS for d in [(4, 4, 4, 4), (6, 4, 6, 10), (4, 24, 48, 48)]])
+@pytest.mark.parametrize("rep,dims", [(r, d) for r in REPS for d in [(4, 4, 4, 4), (6, 4, 6, 10), (4, 24, 48, 48), (2, 2, 2, 2), (4, 2, 2, 6)]])
 def test_operator_f16(oracle, rep, dims):
     h = hrd()
     m0 = -0.3

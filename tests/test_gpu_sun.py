@@ -25,7 +25,7 @@ from paper_2411_18511_amd import inputs
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 CASES = [(3, "fund"), (3, "adj"), (3, "sym"), (3, "asym"), (4, "fund"), (4, "asym")]
-LATS = [(4, 4, 4, 4), (6, 4, 6, 10)]
+LATS = [(4, 4, 4, 4), (6, 4, 6, 10), (2, 2, 2, 2), (4, 2, 2, 6)]
 
 
 @pytest.fixture(scope="module")
