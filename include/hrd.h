@@ -387,6 +387,9 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
      D^_sw = M_ee - D_eo M_oo^{-1} D_oe on even sites,  D^_sw^+ = g5 D^_sw g5.
    M is Hermitian and commutes with g5: two Hermitian 2N x 2N blocks per site
    (spins 0,1 and spins 2,3; row (spin mod 2) N + colour).
+   Formats: the four SU(2) formats (N = 2 or 3) and the SU(3) fundamental in
+   HRD_CPLX3 or HRD_SU3_ROW2 (N = 3, the clover-improved QCD operator); every
+   clover entry point returns HRD_EINVAL for the other dense formats.
    PACKED CLOVER FIELD (M or M^{-1}, one precision): per site and block the
    2N real diagonal entries, then the N(2N-1) complex entries below the
    diagonal in row order ((i, j), i > j, at i(i-1)/2 + j) as (re, im): 4N^2
@@ -396,7 +399,8 @@ hrd_status hrd_cg_solve(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode,
    complex128 [V][4N][4N], row and column index spin * N + colour.         */
 /* ------------------------------------------------------------------------ */
 
-/* Bytes of one packed clover field (M or M^{-1}) of the given precision. */
+/* Bytes of one packed clover field (M or M^{-1}) of the given precision;
+   0 for an invalid lattice, precision or a format without clover support. */
 size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec);
 
 /* Which site matrix hrd_clover_build forms (m = 4 + m0):
