@@ -363,10 +363,18 @@ size_t hrd_cg_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode m
                       accumulation and reductions, and a reliable update (FP64
                       recomputation of the residual) whenever the iterated
                       residual drops below delta times its largest value since
-                      the last update (delta <= 0 selects 0.1).
+                      the last update (delta <= 0 selects 1e-3).  A reliable
+                      update that finds the true residual above twice the
+                      iterated one restarts the search direction from r
+                      (counted in info->restarts) and multiplies delta by 10
+                      (at most 0.5) for the rest of the solve.
      HRD_CG_MIXED16 : as HRD_CG_MIXED with the operator's fields (p, the odd
                       intermediate, D^ p) and the links in F16 storage (FP32
-                      arithmetic); the iterated residual stays FP32.
+                      arithmetic); the iterated residual stays FP32; delta <= 0
+                      selects 3e-2.
+   The workspace of the mixed modes holds 8 low-precision search directions
+   whose solution updates are applied to x together (the same FP64 sums in
+   the same order as one update per iteration).
    maxiter bounds the iterations.  info (may be NULL) is filled in every case.
    Synchronises the stream.  Returns HRD_ENOCONV if the tolerance is not
    reached, HRD_EBREAKDOWN on <p, A p> <= 0 or a non-finite residual. */

@@ -211,11 +211,62 @@ hrd_status read_scalars(const double *sc_dev, double *host, hipStream_t st)
     return check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
+// Two pinned host copies of the CG scalars, each with an event, so that the
+// host reads iteration k's scalars while the stream already runs the first
+// stage of iteration k + 1.
+struct ScalarPipe {
+    hipStream_t st;
+    double *h = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    explicit ScalarPipe(hipStream_t s) : st(s) {}
+    ScalarPipe(const ScalarPipe &) = delete;
+    ScalarPipe &operator=(const ScalarPipe &) = delete;
+    hrd_status init()
+    {
+        hipError_t e = hipHostMalloc((void **)&h, sizeof(double) * 2 * S_COUNT, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+        return check_hip(e, "pinned CG scalars");
+    }
+    hrd_status post(const double *sc_dev, int slot)
+    {
+        hrd_status s = check_hip(hipMemcpyAsync(h + slot * S_COUNT, sc_dev, sizeof(double) * S_COUNT,
+                                                hipMemcpyDeviceToHost, st),
+                                 "hipMemcpyAsync(scalars)");
+        if (s != HRD_OK) return s;
+        return check_hip(hipEventRecord(ev[slot], st), "hipEventRecord");
+    }
+    hrd_status wait(int slot, double *out)
+    {
+        HRD_TRY(check_hip(hipEventSynchronize(ev[slot]), "hipEventSynchronize"));
+        std::memcpy(out, h + slot * S_COUNT, sizeof(double) * S_COUNT);
+        return HRD_OK;
+    }
+    ~ScalarPipe()
+    {
+        if (h) (void)hipStreamSynchronize(st);  // no copy into h may still be in flight
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (h) (void)hipHostFree(h);
+    }
+};
+
+// Default reliable-update thresholds (delta <= 0).  The solution accumulates
+// in FP64, so only the low-precision recurrence of r drifts from the true
+// residual: for FP32 operator fields the drift stays far below 1e-3 of the
+// residual a cycle starts from, for F16 fields it is of order 1e-3 per cycle.
+constexpr double kDeltaMixed = 1e-3;
+constexpr double kDeltaMixed16 = 3e-2;
+
 struct CgBuffers {
     // FP64 (every mode)
     void *r64, *p64, *q64, *Ap64, *t64;
-    // mixed modes: r32 is FP32; p, q, t are FP32 (MIXED) or F16 (MIXED16)
+    // mixed modes: r32 is FP32; p, q, t are FP32 (MIXED) or F16 (MIXED16);
+    // plo is the ring of kPRing search directions, pstride bytes apart, and
+    // ahist holds the alpha of each slot until its update is folded into x
     void *r32, *plo, *qlo, *tlo;
+    size_t pstride;
+    double *ahist;
     double *partials, *sc;
 };
 
@@ -236,7 +287,9 @@ size_t carve_cg(const hrd_lattice *lat, int rep, int mode, void *work, CgBuffers
     } else {
         const size_t hlo = mode == HRD_CG_MIXED16 ? spinor_bytes(lat, rep, HRD_F16, 1) : h32;
         t.r32 = c.take(h32);
-        t.plo = c.take(hlo);
+        t.pstride = (hlo + 255) & ~(size_t)255;
+        t.plo = c.take(t.pstride * kPRing);
+        t.ahist = (double *)c.take(sizeof(double) * kPRing);
         t.qlo = c.take(hlo);
         t.tlo = c.take(hlo);
     }
@@ -679,7 +732,7 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
                   overlap(x, h64, cl32->M, c32) || overlap(x, h64, cl32->Minv, c32);
         if (bad) return finish(fail(HRD_EALIAS, "a clover field overlaps x or the workspace"));
     }
-    if (delta <= 0.0) delta = 0.1;
+    if (delta <= 0.0) delta = mode == HRD_CG_MIXED16 ? kDeltaMixed16 : kDeltaMixed;
 
     CgBuffers w;
     carve_cg(lat, rep, mode, work, &w);
@@ -739,10 +792,19 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     if (!std::isfinite(rr)) return finish(fail(HRD_EBREAKDOWN, "initial residual is not finite"));
     if (std::sqrt(rr) <= target) return finish(HRD_OK);
 
+    ScalarPipe pipe(st);
+    {
+        hrd_status s = pipe.init();
+        if (s != HRD_OK) return finish(s);
+    }
+    int cur = 0;
+    // Each iteration queues the next iteration's D^ p before the host waits
+    // for this iteration's scalars: that stage only writes q, t and the
+    // partials, which a restart or reliable update recomputes anyway.
     if (mode == HRD_CG_F64) {
         CG_HIP(launch_copy(h64, w.r64, w.p64, st), "copy");
+        CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st, cl64), "D^ p");
         while (inf.iters < maxiter) {
-            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st, cl64), "D^ p");
             CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
             CG_HIP(apply_dhat_dag_update_r(rep, HRD_F64, g, U64, w.q64, w.r64, w.t64, m0, w.sc, w.partials, st, cl64),
                    "r -= alpha D^+ q");
@@ -750,9 +812,15 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
             CG_HIP(launch_cg_update_xp64(n64, x, w.p64, w.r64, w.sc, st), "update x, p");
             inf.iters++;
             {
-                hrd_status s = read_scalars(w.sc, sc, st);
+                hrd_status s = pipe.post(w.sc, cur);
                 if (s != HRD_OK) return finish(s);
             }
+            CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st, cl64), "D^ p");
+            {
+                hrd_status s = pipe.wait(cur, sc);
+                if (s != HRD_OK) return finish(s);
+            }
+            cur ^= 1;
             if (sc[S_FLAG] != 0.0)
                 return finish(fail(HRD_EBREAKDOWN, "CG breakdown at iteration %d (pAp = %g, rr = %g)", inf.iters,
                                    sc[S_PAP], sc[S_RRNEW]));
@@ -766,6 +834,7 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
                 if (std::sqrt(rr) <= target) return finish(HRD_OK);
                 inf.restarts++;
                 CG_HIP(launch_copy(h64, w.r64, w.p64, st), "copy");
+                CG_HIP(apply_dhat(rep, HRD_F64, g, U64, w.p64, w.q64, w.t64, m0, false, w.partials, st, cl64), "D^ p");
             }
         }
         hrd_status s = true_residual();
@@ -776,23 +845,43 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     }
 
     // mixed precision with reliable updates; the operator's fields are FP32
-    // (MIXED) or F16 (MIXED16), the iterated residual r32 is FP32 in both
+    // (MIXED) or F16 (MIXED16), the iterated residual r32 is FP32 in both.
+    // The search directions cycle through a ring of kPRing slots; slots
+    // 0 .. j-1 hold directions whose alpha p is not yet in x, which is brought
+    // up to date when the ring is full, before each reliable update and at
+    // the end (the same FP64 sums, in the same order, as updating x every
+    // iteration).
     const int lp = mode == HRD_CG_MIXED16 ? HRD_F16 : HRD_F32;
     const size_t h32 = spinor_bytes(lat, rep, HRD_F32, 1);
-    if (lp == HRD_F32) CG_HIP(launch_copy(h32, w.r32, w.plo, st), "copy");
-    else CG_HIP(launch_convert_spinor_prec(rep, g.Vh, 1, HRD_F32, HRD_F16, w.r32, w.plo, st), "p = r");
+    char *ring = static_cast<char *>(w.plo);
+    auto slot = [&](int i) { return static_cast<void *>(ring + (size_t)i * w.pstride); };
+    auto ring_op = [&](int m, int src, int dst, int beta_mode) {
+        return launch_cg_ring(lp, g.Vh, nc, x, ring, w.pstride, m, src, dst, w.r32, w.sc, w.ahist, beta_mode, st);
+    };
+    if (lp == HRD_F32) CG_HIP(launch_copy(h32, w.r32, slot(0), st), "copy");
+    else CG_HIP(launch_convert_spinor_prec(rep, g.Vh, 1, HRD_F32, HRD_F16, w.r32, slot(0), st), "p = r");
+    int j = 0;
+    CG_HIP(apply_dhat(rep, lp, g, U32, slot(0), w.qlo, w.tlo, m0, false, w.partials, st, cl32), "D^ p");
     double rmax = std::sqrt(rr);
     while (inf.iters < maxiter) {
-        CG_HIP(apply_dhat(rep, lp, g, U32, w.plo, w.qlo, w.tlo, m0, false, w.partials, st, cl32), "D^ p");
-        CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st), "alpha");
+        CG_HIP(launch_cg_alpha(w.partials, hb, w.sc, st, w.ahist + j), "alpha");
         CG_HIP(apply_dhat_dag_update_r(rep, lp, g, U32, w.qlo, w.r32, w.tlo, m0, w.sc, w.partials, st, cl32),
                "r -= alpha D^+ q");
         CG_HIP(launch_cg_beta(w.partials, hb, w.sc, st), "beta");
         inf.iters++;
         {
-            hrd_status s = read_scalars(w.sc, sc, st);
+            hrd_status s = pipe.post(w.sc, cur);
             if (s != HRD_OK) return finish(s);
         }
+        // next direction p = r + beta p_j (a full ring is folded into x first)
+        const int nj = j + 1 < kPRing ? j + 1 : 0;
+        CG_HIP(ring_op(nj == 0 ? kPRing : 0, j, nj, kBetaIter), "advance p");
+        CG_HIP(apply_dhat(rep, lp, g, U32, slot(nj), w.qlo, w.tlo, m0, false, w.partials, st, cl32), "D^ p");
+        {
+            hrd_status s = pipe.wait(cur, sc);
+            if (s != HRD_OK) return finish(s);
+        }
+        cur ^= 1;
         if (sc[S_FLAG] != 0.0)
             return finish(fail(HRD_EBREAKDOWN, "CG breakdown at iteration %d (pAp = %g, rr = %g)", inf.iters,
                                sc[S_PAP], sc[S_RRNEW]));
@@ -800,9 +889,9 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
         inf.iterated_rel_residual = rnew / bnorm;
         rmax = std::max(rmax, rnew);
         if (rnew < delta * rmax || rnew <= target) {
-            // x += alpha p ; then r = b - A x in FP64, r32 = f32(r), beta from the new residual
-            if (lp == HRD_F32) CG_HIP(launch_cg_update_x_mixed(g.Vh, nc, x, w.plo, w.sc, st), "update x");
-            else CG_HIP(launch_cg_update_x_h16(g.Vh, nc, x, w.plo, w.sc, st), "update x");
+            // x += alpha p over the pending slots 0 .. j; then r = b - A x in
+            // FP64, r32 = f32(r), and p = r + (rr / rr_old) p_j into slot 0
+            if (nj > 0) CG_HIP(ring_op(nj, 0, -1, kBetaIter), "update x");
             hrd_status s = true_residual();
             if (s != HRD_OK) return finish(s);
             inf.reliable_updates++;
@@ -810,14 +899,24 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
             inf.true_rel_residual = rt / bnorm;
             if (!std::isfinite(rt)) return finish(fail(HRD_EBREAKDOWN, "non-finite residual"));
             if (rt <= target) return finish(HRD_OK);
+            // a true residual well above the iterated one means the
+            // low-precision recurrence lost track before reaching the
+            // threshold: restart the search direction from r and raise the
+            // threshold for the following cycles
+            const bool drifted = rt > 2.0 * rnew;
+            if (drifted) {
+                inf.restarts++;
+                delta = std::min(0.5, 10.0 * delta);
+            }
             rmax = rt;
-            if (lp == HRD_F32) CG_HIP(launch_cg_update_p32(n32, w.plo, w.r32, w.sc, st), "update p");
-            else CG_HIP(launch_cg_update_p16(g.Vh, nc, w.plo, w.r32, w.sc, st), "update p");
+            CG_HIP(ring_op(0, j, 0, drifted ? kBetaZero : kBetaRatio), "update p");
+            j = 0;
+            CG_HIP(apply_dhat(rep, lp, g, U32, slot(0), w.qlo, w.tlo, m0, false, w.partials, st, cl32), "D^ p");
         } else {
-            if (lp == HRD_F32) CG_HIP(launch_cg_update_xp_mixed(g.Vh, nc, x, w.plo, w.r32, w.sc, st), "update x, p");
-            else CG_HIP(launch_cg_update_xp_h16(g.Vh, nc, x, w.plo, w.r32, w.sc, st), "update x, p");
+            j = nj;
         }
     }
+    if (j > 0) CG_HIP(ring_op(j, 0, -1, kBetaIter), "update x");
     {
         hrd_status s = true_residual();
         if (s != HRD_OK) return finish(s);

@@ -143,17 +143,17 @@ __device__ __forceinline__ double fixed_sum(const double *partials, int nblk)
     return block_sum<kFinThreads>(s);
 }
 
-__global__ __launch_bounds__(kFinThreads) void cg_alpha_kernel(const double *partials, int nblk, double *sc)
+__global__ __launch_bounds__(kFinThreads) void cg_alpha_kernel(const double *partials, int nblk, double *sc,
+                                                                double *hist)
 {
     const double pap = fixed_sum(partials, nblk);
     if (threadIdx.x == 0) {
         sc[S_PAP] = pap;
-        if (!(pap > 0.0) || !isfinite(pap)) {
-            sc[S_FLAG] = 1.0;
-            sc[S_ALPHA] = 0.0;
-        } else {
-            sc[S_ALPHA] = sc[S_RR] / pap;
-        }
+        double alpha = 0.0;
+        if (!(pap > 0.0) || !isfinite(pap)) sc[S_FLAG] = 1.0;
+        else alpha = sc[S_RR] / pap;
+        sc[S_ALPHA] = alpha;
+        if (hist) *hist = alpha;
     }
 }
 
@@ -211,49 +211,53 @@ __global__ __launch_bounds__(kBlock) void cg_update_xp64_kernel(size_t n, void *
     P[i] = make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y);
 }
 
-// thread per (F32 plane q, site j); F64 planes 2q, 2q+1
-__global__ __launch_bounds__(kBlock) void cg_update_xp_mixed_kernel(int Vh, int npl, void *x64, void *p32, const void *r32,
-                                                                   const double *sc)
+// Mixed CG, FP32 search directions kept in a ring of kPRing slots, `stride`
+// bytes apart.  Thread per (F32 plane q, site j); F64 planes 2q, 2q+1.
+// MODE bit 1 (flush): x64 += alpha_s f64(p_s) for the slots s = 0 .. m-1 in
+// order, alpha_s = ahist[s] — the same FP64 operations in the same order as
+// updating x every iteration.  MODE bit 2 (advance): p_dst = r32 + beta p_src
+// with beta chosen by ring_beta().
+__device__ __forceinline__ float ring_beta(const double *sc, int beta_mode)
 {
-    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (long)npl * Vh) return;
-    const int q = (int)(t / Vh);
-    const int j = (int)(t - (long)q * Vh);
-    const double alpha = sc[S_ALPHA];
-    const float beta = (float)sc[S_BETA];
-    float4 *P = reinterpret_cast<float4 *>(p32);
-    double2 *X = reinterpret_cast<double2 *>(x64);
-    const float4 pv = P[t];
-    const float4 rv = reinterpret_cast<const float4 *>(r32)[t];
-    const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
-    double2 x0 = X[i0], x1 = X[i1];
-    x0.x += alpha * (double)pv.x;
-    x0.y += alpha * (double)pv.y;
-    x1.x += alpha * (double)pv.z;
-    x1.y += alpha * (double)pv.w;
-    X[i0] = x0;
-    X[i1] = x1;
-    P[t] = make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+    if (beta_mode == kBetaRatio) return (float)(sc[S_RROLD] > 0.0 ? sc[S_RR] / sc[S_RROLD] : 0.0);
+    if (beta_mode == kBetaZero) return 0.0f;
+    return (float)sc[S_BETA];
 }
 
-__global__ __launch_bounds__(kBlock) void cg_update_x_mixed_kernel(int Vh, int npl, void *x64, const void *p32,
-                                                                  const double *sc)
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void cg_ring_f32_kernel(int Vh, int npl, void *x64, char *ring, size_t stride,
+                                                             int m, int src, int dst, const void *r32,
+                                                             const double *sc, const double *ahist, int beta_mode)
 {
     const long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (long)npl * Vh) return;
-    const int q = (int)(t / Vh);
-    const int j = (int)(t - (long)q * Vh);
-    const double alpha = sc[S_ALPHA];
-    double2 *X = reinterpret_cast<double2 *>(x64);
-    const float4 pv = reinterpret_cast<const float4 *>(p32)[t];
-    const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
-    double2 x0 = X[i0], x1 = X[i1];
-    x0.x += alpha * (double)pv.x;
-    x0.y += alpha * (double)pv.y;
-    x1.x += alpha * (double)pv.z;
-    x1.y += alpha * (double)pv.w;
-    X[i0] = x0;
-    X[i1] = x1;
+    if constexpr ((MODE & 1) != 0) {
+        const int q = (int)(t / Vh);
+        const int j = (int)(t - (long)q * Vh);
+        double2 *X = reinterpret_cast<double2 *>(x64);
+        const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
+        double2 x0 = X[i0], x1 = X[i1];
+#pragma unroll
+        for (int s = 0; s < kPRing; s++) {
+            if (s < m) {
+                const double alpha = ahist[s];
+                const float4 pv = reinterpret_cast<const float4 *>(ring + (size_t)s * stride)[t];
+                x0.x += alpha * (double)pv.x;
+                x0.y += alpha * (double)pv.y;
+                x1.x += alpha * (double)pv.z;
+                x1.y += alpha * (double)pv.w;
+            }
+        }
+        X[i0] = x0;
+        X[i1] = x1;
+    }
+    if constexpr ((MODE & 2) != 0) {
+        const float beta = ring_beta(sc, beta_mode);
+        const float4 pv = reinterpret_cast<const float4 *>(ring + (size_t)src * stride)[t];
+        const float4 rv = reinterpret_cast<const float4 *>(r32)[t];
+        reinterpret_cast<float4 *>(ring + (size_t)dst * stride)[t] =
+            make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void cg_update_p32_kernel(size_t n, void *p32, const void *r32, const double *sc)
@@ -363,9 +367,9 @@ hipError_t launch_finalize(const double *partials, int nblk, int ncol, double *s
     return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st)
+hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st, double *hist)
 {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kFinThreads), 0, st, partials, nblk, sc);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kFinThreads), 0, st, partials, nblk, sc, hist);
     return hipGetLastError();
 }
 
@@ -386,21 +390,6 @@ hipError_t launch_cg_update_r(int prec, size_t n16, void *r, const void *Ap, con
 hipError_t launch_cg_update_xp64(size_t n16, void *x, void *p, const void *r, const double *sc, hipStream_t st)
 {
     hipLaunchKernelGGL(cg_update_xp64_kernel, grid_for(n16), dim3(kBlock), 0, st, n16, x, p, r, sc);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update_xp_mixed(int Vh, int ncomp, void *x64, void *p32, const void *r32, const double *sc,
-                                     hipStream_t st)
-{
-    const int npl = ncomp / 2;
-    hipLaunchKernelGGL(cg_update_xp_mixed_kernel, grid_for((size_t)npl * Vh), dim3(kBlock), 0, st, Vh, npl, x64, p32, r32, sc);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update_x_mixed(int Vh, int ncomp, void *x64, const void *p32, const double *sc, hipStream_t st)
-{
-    const int npl = ncomp / 2;
-    hipLaunchKernelGGL(cg_update_x_mixed_kernel, grid_for((size_t)npl * Vh), dim3(kBlock), 0, st, Vh, npl, x64, p32, sc);
     return hipGetLastError();
 }
 
@@ -439,69 +428,87 @@ hipError_t launch_zero(size_t bytes, void *dst, hipStream_t st)
 
 namespace {
 
-// Mixed CG with p in F16 storage: one thread per site (the F16 site scale
-// covers all components of the site).  MODE 0: x += alpha p, p = r + beta p;
-// MODE 1: x += alpha p; MODE 2: p = r + (rr / rr_old) p.
+// The ring of the mixed CG with p in F16 storage: one thread per site (the
+// F16 site scale covers all components of the site); MODE bits as for
+// cg_ring_f32_kernel.
 template <int NC, int MODE>
-__global__ __launch_bounds__(kBlock) void cg_update_h16_kernel(int Vh, void *x64, void *p16, const void *r32,
-                                                               const double *sc)
+__global__ __launch_bounds__(kBlock) void cg_ring_h16_kernel(int Vh, void *x64, char *ring, size_t stride, int m,
+                                                             int src, int dst, const void *r32, const double *sc,
+                                                             const double *ahist, int beta_mode)
 {
     const int site = blockIdx.x * kBlock + threadIdx.x;
     if (site >= Vh) return;
-    Cx<float> p[NC];
-    SpinorIO<h16>::load<NC>(p16, Vh, site, p);
-    if constexpr (MODE != 2) {
-        const double alpha = sc[S_ALPHA];
+    if constexpr ((MODE & 1) != 0) {
         Cx<double> x[NC];
         SpinorIO<double>::load<NC>(x64, Vh, site, x);
+#pragma unroll 1
+        for (int s = 0; s < m; s++) {
+            const double alpha = ahist[s];
+            Cx<float> p[NC];
+            SpinorIO<h16>::load<NC>(ring + (size_t)s * stride, Vh, site, p);
 #pragma unroll
-        for (int k = 0; k < NC; k++) {
-            x[k].re += alpha * (double)p[k].re;
-            x[k].im += alpha * (double)p[k].im;
+            for (int k = 0; k < NC; k++) {
+                x[k].re += alpha * (double)p[k].re;
+                x[k].im += alpha * (double)p[k].im;
+            }
         }
         SpinorIO<double>::store<NC>(x64, Vh, site, x);
     }
-    if constexpr (MODE != 1) {
-        const float beta = MODE == 0 ? (float)sc[S_BETA] : (float)(sc[S_RROLD] > 0.0 ? sc[S_RR] / sc[S_RROLD] : 0.0);
-        Cx<float> r[NC];
+    if constexpr ((MODE & 2) != 0) {
+        const float beta = ring_beta(sc, beta_mode);
+        Cx<float> p[NC], r[NC];
+        SpinorIO<h16>::load<NC>(ring + (size_t)src * stride, Vh, site, p);
         SpinorIO<float>::load<NC>(r32, Vh, site, r);
 #pragma unroll
         for (int k = 0; k < NC; k++) p[k] = Cx<float>{r[k].re + beta * p[k].re, r[k].im + beta * p[k].im};
-        SpinorIO<h16>::store<NC>(p16, Vh, site, p);
+        SpinorIO<h16>::store<NC>(ring + (size_t)dst * stride, Vh, site, p);
     }
 }
 
 template <int MODE>
-hipError_t launch_h16_update(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
-                             hipStream_t st)
+void launch_ring_h16(int Vh, int ncomp, void *x64, char *ring, size_t stride, int m, int src, int dst,
+                     const void *r32, const double *sc, const double *ahist, int beta_mode, hipStream_t st)
 {
     const dim3 grid((unsigned)((Vh + kBlock - 1) / kBlock));
+#define HRD_RING16(NC) \
+    hipLaunchKernelGGL((cg_ring_h16_kernel<NC, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, ring, stride, m, src, dst, r32, sc, ahist, beta_mode)
     switch (ncomp) {
-        case 8: hipLaunchKernelGGL((cg_update_h16_kernel<8, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
-        case 12: hipLaunchKernelGGL((cg_update_h16_kernel<12, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
-        case 16: hipLaunchKernelGGL((cg_update_h16_kernel<16, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
-        case 24: hipLaunchKernelGGL((cg_update_h16_kernel<24, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
-        default: hipLaunchKernelGGL((cg_update_h16_kernel<32, MODE>), grid, dim3(kBlock), 0, st, Vh, x64, p16, r32, sc); break;
+        case 8: HRD_RING16(8); break;
+        case 12: HRD_RING16(12); break;
+        case 16: HRD_RING16(16); break;
+        case 24: HRD_RING16(24); break;
+        default: HRD_RING16(32); break;
     }
-    return hipGetLastError();
+#undef HRD_RING16
+}
+
+template <int MODE>
+void launch_ring_f32(int Vh, int ncomp, void *x64, char *ring, size_t stride, int m, int src, int dst,
+                     const void *r32, const double *sc, const double *ahist, int beta_mode, hipStream_t st)
+{
+    const int npl = ncomp / 2;
+    hipLaunchKernelGGL((cg_ring_f32_kernel<MODE>), grid_for((size_t)npl * Vh), dim3(kBlock), 0, st, Vh, npl, x64,
+                       ring, stride, m, src, dst, r32, sc, ahist, beta_mode);
 }
 
 }  // namespace
 
-hipError_t launch_cg_update_xp_h16(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
-                                   hipStream_t st)
+hipError_t launch_cg_ring(int prec, int Vh, int ncomp, void *x64, void *ring, size_t stride, int m, int src,
+                          int dst, const void *r32, const double *sc, const double *ahist, int beta_mode, hipStream_t st)
 {
-    return launch_h16_update<0>(Vh, ncomp, x64, p16, r32, sc, st);
-}
-
-hipError_t launch_cg_update_x_h16(int Vh, int ncomp, void *x64, const void *p16, const double *sc, hipStream_t st)
-{
-    return launch_h16_update<1>(Vh, ncomp, x64, const_cast<void *>(p16), nullptr, sc, st);
-}
-
-hipError_t launch_cg_update_p16(int Vh, int ncomp, void *p16, const void *r32, const double *sc, hipStream_t st)
-{
-    return launch_h16_update<2>(Vh, ncomp, nullptr, p16, r32, sc, st);
+    if (m < 0 || m > kPRing || (m == 0 && dst < 0)) return hipErrorInvalidValue;
+    char *rg = static_cast<char *>(ring);
+    const bool fl = m > 0, adv = dst >= 0;
+    if (prec == HRD_F16) {
+        if (fl && adv) launch_ring_h16<3>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+        else if (fl) launch_ring_h16<1>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+        else launch_ring_h16<2>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+    } else {
+        if (fl && adv) launch_ring_f32<3>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+        else if (fl) launch_ring_f32<1>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+        else launch_ring_f32<2>(Vh, ncomp, x64, rg, stride, m, src, dst, r32, sc, ahist, beta_mode, st);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace hrd

@@ -94,8 +94,9 @@ enum ScalarSlot {
     S_RROLD = 7,   // ||r||^2 before the last beta stage
     S_COUNT = 8
 };
-// Sum partials of ||D^p||^2 and set alpha = rr / pAp (flag breakdown).
-hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st);
+// Sum partials of ||D^p||^2 and set alpha = rr / pAp (flag breakdown); also
+// store alpha at *hist when hist is not null.
+hipError_t launch_cg_alpha(const double *partials, int nblk, double *sc, hipStream_t st, double *hist = nullptr);
 // Sum partials of ||r||^2 into rr_new and set beta = rr_new / rr, rr = rr_new.
 hipError_t launch_cg_beta(const double *partials, int nblk, double *sc, hipStream_t st);
 // r <- r - alpha Ap (F64 or F32 fields), partials of ||r||^2 (FP64).
@@ -103,19 +104,19 @@ hipError_t launch_cg_update_r(int prec, size_t n, void *r, const void *Ap, const
                               hipStream_t st);
 // F64 CG: x <- x + alpha p ; p <- r + beta p.
 hipError_t launch_cg_update_xp64(size_t n, void *x, void *p, const void *r, const double *sc, hipStream_t st);
-// Mixed CG: x64 <- x64 + alpha f64(p32) ; p32 <- r32 + beta p32.  ncomp
-// complex components per site, Vh sites (layout conversion inside).
-hipError_t launch_cg_update_xp_mixed(int Vh, int ncomp, void *x64, void *p32, const void *r32,
-                                     const double *sc, hipStream_t st);
-// Mixed CG, reliable-update iteration: x64 <- x64 + alpha f64(p32).
-hipError_t launch_cg_update_x_mixed(int Vh, int ncomp, void *x64, const void *p32, const double *sc, hipStream_t st);
-// p32 <- r32 + beta p32 with beta = rr / rr_old (after a reliable update).
+// p32 <- r32 + beta p32 with beta = rr / rr_old (batched CG, after a reliable update).
 hipError_t launch_cg_update_p32(size_t n16, void *p32, const void *r32, const double *sc, hipStream_t st);
-// The same three updates with p in F16 storage (r stays F32, x F64).
-hipError_t launch_cg_update_xp_h16(int Vh, int ncomp, void *x64, void *p16, const void *r32, const double *sc,
-                                   hipStream_t st);
-hipError_t launch_cg_update_x_h16(int Vh, int ncomp, void *x64, const void *p16, const double *sc, hipStream_t st);
-hipError_t launch_cg_update_p16(int Vh, int ncomp, void *p16, const void *r32, const double *sc, hipStream_t st);
+// Mixed CG search directions: a ring of kPRing low-precision (F32 or F16)
+// fields, `stride` bytes apart, whose solution updates are deferred.  Flush
+// (m > 0): x64 += alpha_s p_s for the slots s = 0 .. m-1 in order,
+// alpha_s = ahist[s].  Advance (dst >= 0, after the flush when both):
+// p_dst = r32 + beta p_src with beta = sc[S_BETA] (kBetaIter), rr / rr_old
+// (kBetaRatio, after a reliable update) or 0 (kBetaZero, restart).
+constexpr int kPRing = 8;
+enum RingBeta { kBetaIter = 0, kBetaRatio = 1, kBetaZero = 2 };
+hipError_t launch_cg_ring(int prec, int Vh, int ncomp, void *x64, void *ring, size_t stride, int m, int src,
+                          int dst, const void *r32, const double *sc, const double *ahist, int beta_mode,
+                          hipStream_t st);
 // Reliable update: r64 = b - Ax64 ; r32 = f32(r64) ; partials of ||r64||^2.
 hipError_t launch_cg_residual_mixed(int Vh, int ncomp, const void *b, const void *Ax, void *r64, void *r32,
                                     double *partials, hipStream_t st);

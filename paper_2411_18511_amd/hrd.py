@@ -451,10 +451,12 @@ def cg_workspace_bytes(dims, rep, mode):
     return _lib.hrd_cg_workspace_bytes(ctypes.byref(lattice(dims)), _REPS[rep], _MODES[mode])
 
 
-def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=10000, delta=0.1, work=None,
+def cg_solve(U64, b, m0, tol, dims, rep, mode="f64", U32=None, x0=None, maxiter=10000, delta=0.0, work=None,
              allow_noconv=False):
     """Solve (D^+ D^) x = b on even sites; returns (x, info dict).  U32 is the
-    reduced-precision gauge copy: FP32 for mode 'mixed', F16 for 'mixed16'."""
+    reduced-precision gauge copy: FP32 for mode 'mixed', F16 for 'mixed16'.
+    delta is the reliable-update threshold (0: the library's default for the
+    mode)."""
     rep, mode = _REPS[rep], _MODES[mode]
     nb = spinor_bytes(dims, rep, F64, 1)
     _need(b, nb, "b")
@@ -576,7 +578,7 @@ class CloverOp:
 
 
 def cg_solve_clover(U64, clov64, b, tol, dims, rep, mode="f64", U32=None, clov32=None, x0=None, maxiter=10000,
-                    delta=0.1, work=None, allow_noconv=False):
+                    delta=0.0, work=None, allow_noconv=False):
     """Solve (D^_sw^+ D^_sw) x = b on even sites; returns (x, info dict)."""
     rep, mode = _REPS[rep], _MODES[mode]
     nb = spinor_bytes(dims, rep, F64, 1)

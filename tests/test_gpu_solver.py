@@ -113,6 +113,58 @@ def test_cg_warm_start_and_determinism(oracle):
     assert i5["iters"] == 0 and i5["true_rel_residual"] <= 1e-10
 
 
+@pytest.mark.parametrize("mode", ["mixed", "mixed16"])
+@pytest.mark.parametrize("delta", [0.1, 1e-8])
+def test_mixed_cg_early_exit(oracle, mode, delta):
+    """Mixed CG stopped after k iterations, on both sides of a wrap of the
+    8-slot ring of search directions whose solution updates are deferred: the
+    returned x must hold every direction's update.  FP32 inner operator: x is
+    the oracle's k-th CG iterate up to FP32 rounding; F16: the true residual of
+    x agrees with the iterated one (a missing update would leave the true
+    residual at the size of an earlier iterate's)."""
+    h = hrd()
+    dims = (4, 4, 4, 8)
+    m0 = -0.2
+    F = Field(dims, "fund", seed=51, kind="smeared")
+    U = F.U32 if mode == "mixed" else h.convert_gauge_prec(F.U64, dims, "fund", "f16")
+    b_np = oracle.restrict(F.spinor(52), 0)
+    b = F.pack(b_np, "f64", "even")
+    for k in (1, 7, 8, 9, 16, 17):
+        x, info = h.cg_solve(F.U64, b, m0, 1e-10, dims, "fund", mode=mode, U32=U, maxiter=k, delta=delta,
+                             allow_noconv=True)
+        assert info["status"] == "HRD_ENOCONV" and info["iters"] == k
+        xe = F.unpack(x, "f64", "even")
+        res = oracle.true_residual(F.U_orc, b_np, xe, m0)
+        assert abs(info["true_rel_residual"] - res) <= 1e-6 * res
+        it = info["iterated_rel_residual"]
+        print(f"{mode} delta={delta} k={k}: true {res:.3e} iterated {it:.3e} updates {info['reliable_updates']}")
+        if mode == "mixed":
+            x_orc, _ = oracle.cg(F.U_orc, b_np, m0, tol=1e-30, maxiter=k)
+            assert rel_err(xe, x_orc) < 1e-4, (k, rel_err(xe, x_orc))
+        else:
+            assert abs(res - it) <= 0.1 * it + 2e-3, (k, res, it)
+
+
+@pytest.mark.parametrize("mode,delta", [("mixed", 1e-4), ("mixed16", 1e-4), ("mixed16", 1e-7)])
+def test_mixed_cg_few_reliable_updates(oracle, mode, delta):
+    """Small reliable-update thresholds: many passes through the ring of
+    search directions between updates of the residual (and, for F16 fields,
+    thresholds below the recurrence's drift, which the solver detects and
+    raises); the true residual still reaches the tolerance."""
+    h = hrd()
+    dims = (8, 4, 4, 8)
+    m0 = -0.3
+    tol = 1e-10
+    F = Field(dims, "adj", seed=61, kind="smeared")
+    U = F.U32 if mode == "mixed" else h.convert_gauge_prec(F.U64, dims, "adj", "f16")
+    b_np = oracle.restrict(F.spinor(62), 0)
+    b = F.pack(b_np, "f64", "even")
+    x, info = h.cg_solve(F.U64, b, m0, tol, dims, "adj", mode=mode, U32=U, delta=delta, maxiter=2000)
+    print(f"{mode}: {info}")
+    res = oracle.true_residual(F.U_orc, b_np, F.unpack(x, "f64", "even"), m0)
+    assert res <= tol and info["iters"] > 24
+
+
 def test_cg_errors(oracle):
     h = hrd()
     dims = (4, 4, 4, 4)
