@@ -549,7 +549,9 @@ size_t hrd_cg_batched_workspace_bytes(const hrd_problem *probs, int nprob);
    fields b_k, dst the FP64 x_k (initial guess on entry).  The FP32 operator
    stages run batched (one launch per stage for all problems), reductions and
    scalars are per right-hand side in FP64, converged right-hand sides are
-   masked out.  infos has one entry per right-hand side, in problem order.
+   masked out.  delta and the restart on drift as for HRD_CG_MIXED (per
+   right-hand side).  infos has one entry per right-hand side, in problem
+   order.
    Synchronises.  Returns HRD_ENOCONV if any system misses tol. */
 hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol, int maxiter,
                                 double delta, const hrd_tune *tune, void *work,

@@ -251,13 +251,6 @@ struct ScalarPipe {
     }
 };
 
-// Default reliable-update thresholds (delta <= 0).  The solution accumulates
-// in FP64, so only the low-precision recurrence of r drifts from the true
-// residual: for FP32 operator fields the drift stays far below 1e-3 of the
-// residual a cycle starts from, for F16 fields it is of order 1e-3 per cycle.
-constexpr double kDeltaMixed = 1e-3;
-constexpr double kDeltaMixed16 = 3e-2;
-
 struct CgBuffers {
     // FP64 (every mode)
     void *r64, *p64, *q64, *Ap64, *t64;

@@ -629,7 +629,7 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
     if (!work) return fail(HRD_EINVAL, "NULL workspace");
     hrd_tune t = resolve_tune(tune);
     HRD_TRY(check_tune(t));
-    if (delta <= 0.0) delta = 0.1;
+    if (delta <= 0.0) delta = kDeltaMixed;
     const size_t need = bcg_carve(probs, nprob, nullptr, nullptr);
     if (work_bytes < need) return fail(HRD_ESIZE, "workspace %zu < %zu bytes", work_bytes, need);
     for (int i = 0; i < nprob; i++) {
@@ -670,7 +670,7 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
         }
     std::vector<int> mode(total, M_NORMAL);
     std::vector<double> sc((size_t)S_COUNT * total);
-    std::vector<double> bnorm(total), rmax(total);
+    std::vector<double> bnorm(total), rmax(total), dlt(total, delta);
     std::vector<hrd_cg_info> inf(total);
     std::vector<hrd_status> stat(total, HRD_OK);
 
@@ -768,7 +768,7 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
             const double rn = std::sqrt(c[S_RR]);
             inf[r].iterated_rel_residual = rn / bnorm[r];
             rmax[r] = std::max(rmax[r], rn);
-            if (rn < delta * rmax[r] || rn <= tol * bnorm[r]) {
+            if (rn < dlt[r] * rmax[r] || rn <= tol * bnorm[r]) {
                 mode[r] = M_RELIABLE;
                 reliable.push_back(r);
             }
@@ -793,9 +793,19 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
                     mode[r] = M_DONE;
                     active--;
                 } else {
-                    rmax[r] = rt;
                     mode[r] = M_NORMAL;
-                    BT(launch_cg_update_p32(rdh[r].n16, rdh[r].p32, rdh[r].r32, w.sc + (size_t)r * S_COUNT, st), "p");
+                    // drift of the FP32 recurrence beyond the threshold: restart
+                    // p from r and raise this right-hand side's threshold
+                    const double rn = inf[r].iterated_rel_residual * bnorm[r];
+                    if (rt > 2.0 * rn) {
+                        inf[r].restarts++;
+                        dlt[r] = std::min(0.5, 10.0 * dlt[r]);
+                        BT(launch_copy(hd[prob_of[r]].fbytes, rdh[r].r32, rdh[r].p32, st), "p = r");
+                    } else {
+                        BT(launch_cg_update_p32(rdh[r].n16, rdh[r].p32, rdh[r].r32, w.sc + (size_t)r * S_COUNT, st),
+                           "p");
+                    }
+                    rmax[r] = rt;
                 }
             }
             HRD_TRY(upload_mode());

@@ -113,6 +113,12 @@ hipError_t launch_cg_update_p32(size_t n16, void *p32, const void *r32, const do
 // p_dst = r32 + beta p_src with beta = sc[S_BETA] (kBetaIter), rr / rr_old
 // (kBetaRatio, after a reliable update) or 0 (kBetaZero, restart).
 constexpr int kPRing = 8;
+// Default reliable-update thresholds (delta <= 0).  The solution accumulates
+// in FP64, so only the low-precision recurrence of r drifts from the true
+// residual: for FP32 operator fields the drift stays far below 1e-3 of the
+// residual a cycle starts from, for F16 fields it is of order 1e-3 per cycle.
+constexpr double kDeltaMixed = 1e-3;
+constexpr double kDeltaMixed16 = 3e-2;
 enum RingBeta { kBetaIter = 0, kBetaRatio = 1, kBetaZero = 2 };
 hipError_t launch_cg_ring(int prec, int Vh, int ncomp, void *x64, void *ring, size_t stride, int m, int src,
                           int dst, const void *r32, const double *sc, const double *ahist, int beta_mode,

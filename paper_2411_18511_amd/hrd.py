@@ -668,7 +668,7 @@ def dirac_apply_batched(problems, parity, dagger=False, tune=None, work=None, de
                                         _tune_ptr(tune), _ptr(work), wb, _stream()))
 
 
-def cg_solve_batched(problems, tol, maxiter=10000, delta=0.1, tune=None, work=None, device="cuda",
+def cg_solve_batched(problems, tol, maxiter=10000, delta=0.0, tune=None, work=None, device="cuda",
                      allow_noconv=False):
     wb = _lib.hrd_cg_batched_workspace_bytes(problems, len(problems))
     if work is None:
