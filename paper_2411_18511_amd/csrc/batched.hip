@@ -38,7 +38,10 @@ namespace {
 
 constexpr int kMaxProb = 64;
 constexpr int kMaxRhs = 64;
-constexpr int kNumBuf = 6;
+// buffer slots of a problem: operator stages use 0..4; the batched CG keeps
+// its ring of search directions in slots kBufRing .. kBufRing + kPRing - 1
+constexpr int kBufRing = 4;
+constexpr int kNumBuf = kBufRing + kPRing;
 constexpr int kVecBlocks = 64;  // x-blocks per right-hand side in vector kernels
 
 struct BatchDesc {
@@ -56,11 +59,13 @@ struct BatchDesc {
     char *buf[kNumBuf];
 };
 
-// Per right-hand side view for the vector stages of the batched CG.
+// Per right-hand side view for the vector stages of the batched CG: p32 is
+// the right-hand side's field in ring slot 0, slot s at p32 + s * pslot.
 struct RhsDesc {
     int Vh, ncomp, nsb, pad;
-    size_t n16;  // 16-byte elements of one FP32 half field
-    char *x64, *r32, *p32, *Ap32;
+    size_t n16;    // 16-byte elements of one FP32 half field
+    size_t pslot;  // bytes between ring slots
+    char *x64, *r32, *p32;
 };
 
 enum BatchMode { M_NORMAL = 0, M_RELIABLE = 1, M_DONE = 2 };
@@ -101,11 +106,13 @@ __device__ __forceinline__ void dir_term(const typename LinkIO<REP, float>::Link
 // after another (each with all 8 neighbour loads in flight), so the
 // register footprint does not grow with G.  EPI2: out = m self + acc / (2m),
 // plus per-right-hand-side ||out||^2 partials when `partials` is not NULL;
-// else out = -acc / 2.
-template <int REP, bool DAG, bool EPI2>
+// else out = -acc / 2.  RUPD (with EPI2, batched CG): dst is the residual r,
+// updated as r -= alpha out with the right-hand side's alpha from sc, and the
+// partials are those of ||r||^2.
+template <int REP, bool DAG, bool EPI2, bool RUPD>
 __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp, int G, int parity, int src_id,
                                              int self_id, int dst_id, const int *mode, double *partials,
-                                             int part_stride)
+                                             int part_stride, const double *sc)
 {
     constexpr int NC = 4 * NCol<REP>::value;
     constexpr int SF = DAG ? +1 : -1;
@@ -169,13 +176,21 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
                 SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)rhs * d.fbytes, g.Vh, idx, sv);
 #pragma unroll
                 for (int c = 0; c < NC; c++) out[c] = axpby(ca, sv[c], cb, acc[c]);
+                if constexpr (RUPD) {
+                    const float alpha = (float)sc[(size_t)(d.rhs_base + rhs) * S_COUNT + S_ALPHA];
+                    Cx<float> rv[NC];
+                    SpinorIO<float>::template load<NC>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, rv);
+#pragma unroll
+                    for (int c = 0; c < NC; c++) out[c] = Cx<float>{rv[c].re - alpha * out[c].re,
+                                                                    rv[c].im - alpha * out[c].im};
+                }
 #pragma unroll
                 for (int c = 0; c < NC; c++) nrm += (double)out[c].re * out[c].re + (double)out[c].im * out[c].im;
             } else {
 #pragma unroll
                 for (int c = 0; c < NC; c++) out[c] = cb * acc[c];
             }
-            SpinorIO<float>::template store<NC, true>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, out);
+            SpinorIO<float>::template store<NC, !RUPD>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, out);
         }
         if (EPI2 && partials != nullptr) {
             // block-wide sum of ||out||^2, only when the caller wants it (a
@@ -194,10 +209,11 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
     }
 }
 
-template <bool DAG, bool EPI2>
+template <bool DAG, bool EPI2, bool RUPD>
 __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs, int nprob, int ntiles, int G,
                                                           int parity, int src_id, int self_id, int dst_id,
-                                                          const int *mode, double *partials, int part_stride)
+                                                          const int *mode, double *partials, int part_stride,
+                                                          const double *sc)
 {
     // each XCD walks its own contiguous range of tiles (gridDim.x is a multiple of 8)
     const int xcd = blockIdx.x % kNumXcd;
@@ -215,20 +231,20 @@ __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs
         const int grp = local - sb * d.ngroups;
         switch (d.rep) {
             case HRD_FUND:
-                batched_tile<HRD_FUND, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
-                                                  part_stride);
+                batched_tile<HRD_FUND, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode,
+                                                  partials, part_stride, sc);
                 break;
             case HRD_ADJ:
-                batched_tile<HRD_ADJ, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
-                                                 part_stride);
+                batched_tile<HRD_ADJ, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode,
+                                                 partials, part_stride, sc);
                 break;
             case HRD_FUND_SU2:
-                batched_tile<HRD_FUND_SU2, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
-                                                      part_stride);
+                batched_tile<HRD_FUND_SU2, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode,
+                                                      partials, part_stride, sc);
                 break;
             default:
-                batched_tile<HRD_ADJ_SU2, DAG, EPI2>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
-                                                     part_stride);
+                batched_tile<HRD_ADJ_SU2, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode,
+                                                     partials, part_stride, sc);
                 break;
         }
     }
@@ -248,67 +264,59 @@ __device__ __forceinline__ double blk_sum256(double v)
     return s;
 }
 
-// r <- r - alpha Ap ; partials of ||r||^2 (grid: kVecBlocks x nrhs)
-__global__ __launch_bounds__(256) void bcg_update_r_kernel(const RhsDesc *rd, const int *mode, const double *sc,
-                                                           double *partials)
-{
-    const int r = blockIdx.y;
-    if (mode[r] == M_DONE) return;
-    const RhsDesc d = rd[r];
-    const float alpha = (float)sc[r * S_COUNT + S_ALPHA];
-    double s = 0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < d.n16; i += (size_t)gridDim.x * 256) {
-        float4 *R = reinterpret_cast<float4 *>(d.r32) + i;
-        const float4 a = reinterpret_cast<const float4 *>(d.Ap32)[i];
-        float4 v = *R;
-        v.x -= alpha * a.x;
-        v.y -= alpha * a.y;
-        v.z -= alpha * a.z;
-        v.w -= alpha * a.w;
-        *R = v;
-        s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
-    }
-    s = blk_sum256(s);
-    if (threadIdx.x == 0) partials[(size_t)r * kVecBlocks + blockIdx.x] = s;
-}
-
-// x64 += alpha f64(p32) ; p32 = r32 + beta p32 for mode == M_NORMAL;
-// only the x update for mode == M_RELIABLE when only_x is set.
-__global__ __launch_bounds__(256) void bcg_update_xp_kernel(const RhsDesc *rd, const int *mode, const double *sc,
-                                                            int only_x)
+// Ring of FP32 search directions shared in lockstep by all right-hand sides
+// (grid: kVecBlocks x nrhs, thread per (F32 plane q, site j), F64 planes 2q,
+// 2q+1).  For right-hand side r, unless done: when `flush_all` is set or r is
+// in a reliable update, x64 += alpha_s f64(p_s) over its pending slots
+// s = lo[r] .. j in order (alpha_s = ahist[r * kPRing + s]); when r is normal
+// and dst >= 0, p_dst = r32 + beta p_j.
+__global__ __launch_bounds__(256) void bcg_ring_kernel(const RhsDesc *rd, const int *mode, const int *lo,
+                                                       const double *sc, const double *ahist, int j, int dst,
+                                                       int flush_all)
 {
     const int r = blockIdx.y;
     const int md = mode[r];
-    if (only_x ? md != M_RELIABLE : md != M_NORMAL) return;
+    if (md == M_DONE) return;
+    const bool flush = flush_all || md == M_RELIABLE;
+    const bool adv = md == M_NORMAL && dst >= 0;
+    if (!flush && !adv) return;
     const RhsDesc d = rd[r];
-    const double alpha = sc[r * S_COUNT + S_ALPHA];
+    const int s0 = lo[r];
+    const double *al = ahist + (size_t)r * kPRing;
     const float beta = (float)sc[r * S_COUNT + S_BETA];
     const int npl = d.ncomp / 2;
     const long n = (long)npl * d.Vh;
     for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) {
-        const int q = (int)(t / d.Vh);
-        const int j = (int)(t - (long)q * d.Vh);
-        float4 *P = reinterpret_cast<float4 *>(d.p32) + t;
-        const float4 pv = *P;
-        double2 *X = reinterpret_cast<double2 *>(d.x64);
-        const size_t i0 = (size_t)(2 * q) * d.Vh + j, i1 = i0 + d.Vh;
-        double2 x0 = X[i0], x1 = X[i1];
-        x0.x += alpha * (double)pv.x;
-        x0.y += alpha * (double)pv.y;
-        x1.x += alpha * (double)pv.z;
-        x1.y += alpha * (double)pv.w;
-        X[i0] = x0;
-        X[i1] = x1;
-        if (!only_x) {
+        if (flush) {
+            const int q = (int)(t / d.Vh);
+            const int jj = (int)(t - (long)q * d.Vh);
+            double2 *X = reinterpret_cast<double2 *>(d.x64);
+            const size_t i0 = (size_t)(2 * q) * d.Vh + jj, i1 = i0 + d.Vh;
+            double2 x0 = X[i0], x1 = X[i1];
+            for (int sl = s0; sl <= j; sl++) {
+                const double alpha = al[sl];
+                const float4 pv = reinterpret_cast<const float4 *>(d.p32 + (size_t)sl * d.pslot)[t];
+                x0.x += alpha * (double)pv.x;
+                x0.y += alpha * (double)pv.y;
+                x1.x += alpha * (double)pv.z;
+                x1.y += alpha * (double)pv.w;
+            }
+            X[i0] = x0;
+            X[i1] = x1;
+        }
+        if (adv) {
+            const float4 pv = reinterpret_cast<const float4 *>(d.p32 + (size_t)j * d.pslot)[t];
             const float4 rv = reinterpret_cast<const float4 *>(d.r32)[t];
-            *P = make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
+            reinterpret_cast<float4 *>(d.p32 + (size_t)dst * d.pslot)[t] =
+                make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
         }
     }
 }
 
-// Per right-hand side: alpha = rr / pAp from the hop partials (count nsb).
+// Per right-hand side: alpha = rr / pAp from the hop partials (count nsb),
+// also kept in ring slot j of ahist.
 __global__ __launch_bounds__(256) void bcg_alpha_kernel(const RhsDesc *rd, const int *mode, const double *partials,
-                                                        int part_stride, double *sc)
+                                                        int part_stride, double *sc, double *ahist, int j)
 {
     const int r = blockIdx.x;
     if (mode[r] == M_DONE) return;
@@ -319,22 +327,24 @@ __global__ __launch_bounds__(256) void bcg_alpha_kernel(const RhsDesc *rd, const
     if (threadIdx.x == 0) {
         double *c = sc + r * S_COUNT;
         c[S_PAP] = s;
-        if (!(s > 0.0) || !isfinite(s)) {
-            c[S_FLAG] = 1.0;
-            c[S_ALPHA] = 0.0;
-        } else {
-            c[S_ALPHA] = c[S_RR] / s;
-        }
+        double alpha = 0.0;
+        if (!(s > 0.0) || !isfinite(s)) c[S_FLAG] = 1.0;
+        else alpha = c[S_RR] / s;
+        c[S_ALPHA] = alpha;
+        ahist[(size_t)r * kPRing + j] = alpha;
     }
 }
 
-// Per right-hand side: rr_new from the update partials, beta = rr_new / rr.
-__global__ __launch_bounds__(256) void bcg_beta_kernel(const int *mode, const double *partials, double *sc)
+// Per right-hand side: rr_new from the partials of the residual-updating
+// stage (count nsb), beta = rr_new / rr.
+__global__ __launch_bounds__(256) void bcg_beta_kernel(const RhsDesc *rd, const int *mode, const double *partials,
+                                                       int part_stride, double *sc)
 {
     const int r = blockIdx.x;
     if (mode[r] == M_DONE) return;
+    const int n = rd[r].nsb;
     double s = 0;
-    for (int k = threadIdx.x; k < kVecBlocks; k += 256) s += partials[(size_t)r * kVecBlocks + k];
+    for (int k = threadIdx.x; k < n; k += 256) s += partials[(size_t)r * part_stride + k];
     s = blk_sum256(s);
     if (threadIdx.x == 0) {
         double *c = sc + r * S_COUNT;
@@ -453,26 +463,33 @@ int build_descs(const hrd_problem *probs, int nprob, const hrd_tune &t, std::vec
     return tiles;
 }
 
-template <bool DAG, bool EPI2>
+template <bool DAG, bool EPI2, bool RUPD>
 hipError_t launch_stage_t(const hrd_tune &t, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity,
-                          int s, int self, int dst, const int *mode, double *parts, int ps)
+                          int s, int self, int dst, const int *mode, double *parts, int ps, const double *sc)
 {
     int grid = kNumCu * t.blocks_per_cu;
     grid = (grid / kNumXcd) * kNumXcd;
-    hipLaunchKernelGGL((batched_hop_kernel<DAG, EPI2>), dim3(grid), dim3(t.sites_per_tile), 0, st, dd, nprob, ntiles,
-                       t.rhs_per_tile, parity, s, self, dst, mode, parts, ps);
+    hipLaunchKernelGGL((batched_hop_kernel<DAG, EPI2, RUPD>), dim3(grid), dim3(t.sites_per_tile), 0, st, dd, nprob,
+                       ntiles, t.rhs_per_tile, parity, s, self, dst, mode, parts, ps, sc);
     return hipGetLastError();
 }
 
+// One hopping stage over every problem.  sc != NULL (batched CG, with epi2
+// and dagger): the stage updates the residual in buffer dst (r -= alpha Ap).
 hipError_t launch_stage(const hrd_tune &t, bool dag, bool epi2, hipStream_t st, const BatchDesc *dd, int nprob,
-                        int ntiles, int parity, int s, int self, int dst, const int *mode, double *parts, int ps)
+                        int ntiles, int parity, int s, int self, int dst, const int *mode, double *parts, int ps,
+                        const double *sc = nullptr)
 {
-    if (dag) {
-        if (epi2) return launch_stage_t<true, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
-        return launch_stage_t<true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+    if (sc) {
+        if (!dag || !epi2) return hipErrorInvalidValue;
+        return launch_stage_t<true, true, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
     }
-    if (epi2) return launch_stage_t<false, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
-    return launch_stage_t<false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps);
+    if (dag) {
+        if (epi2) return launch_stage_t<true, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+        return launch_stage_t<true, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+    }
+    if (epi2) return launch_stage_t<false, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+    return launch_stage_t<false, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
 }
 
 // Workspace of the batched apply: descriptor table, then one FP32 odd
@@ -570,11 +587,13 @@ struct BcgWork {
     BatchDesc *dd;
     RhsDesc *rd;
     int *mode;
-    double *sc, *parts, *vparts;
+    double *sc, *parts, *ahist;
     // FP64 temporaries sized for the largest problem (reliable updates)
     void *q64, *Ap64, *t64, *r64;
-    // per problem FP32 buffers (nrhs fields each): p, t (odd), q, Ap, r
-    char *f32[kMaxProb][5];
+    // per problem FP32 buffers (nrhs fields each): t (odd), q, r, and the
+    // ring of kPRing search-direction slots
+    char *f32[kMaxProb][3];
+    char *ring[kMaxProb];
 };
 
 size_t bcg_carve(const hrd_problem *probs, int nprob, void *work, BcgWork *w)
@@ -592,17 +611,18 @@ size_t bcg_carve(const hrd_problem *probs, int nprob, void *work, BcgWork *w)
     }
     t.dd = (BatchDesc *)c.take(sizeof(BatchDesc) * kMaxProb);
     t.rd = (RhsDesc *)c.take(sizeof(RhsDesc) * total);
-    t.mode = (int *)c.take(sizeof(int) * total);
+    t.mode = (int *)c.take(sizeof(int) * 2 * total);  // modes, then first pending ring slots
     t.sc = (double *)c.take(sizeof(double) * S_COUNT * total);
     t.parts = (double *)c.take(sizeof(double) * (size_t)std::max(max_nsb, kRedBlocks) * total);
-    t.vparts = (double *)c.take(sizeof(double) * kVecBlocks * total);
+    t.ahist = (double *)c.take(sizeof(double) * kPRing * total);
     t.q64 = c.take(max64);
     t.Ap64 = c.take(max64);
     t.t64 = c.take(max64);
     t.r64 = c.take(max64);
     for (int i = 0; i < nprob; i++) {
         const size_t fb = spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F32, 1) * probs[i].nrhs;
-        for (int k = 0; k < 5; k++) t.f32[i][k] = (char *)c.take(fb);
+        for (int k = 0; k < 3; k++) t.f32[i][k] = (char *)c.take(fb);
+        t.ring[i] = (char *)c.take(fb * kPRing);
     }
     if (w) *w = t;
     return c.used();
@@ -646,9 +666,11 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
     int max_nsb;
     const int ntiles = build_descs(probs, nprob, t, hd, &max_nsb);
     const int part_stride = std::max(max_nsb, kRedBlocks);
-    for (int i = 0; i < nprob; i++)
-        for (int k = 0; k < 5; k++) hd[i].buf[k] = w.f32[i][k];
-    enum { B_P = 0, B_T = 1, B_Q = 2, B_AP = 3, B_R = 4 };
+    for (int i = 0; i < nprob; i++) {
+        for (int k = 0; k < 3; k++) hd[i].buf[k] = w.f32[i][k];
+        for (int sl = 0; sl < kPRing; sl++) hd[i].buf[kBufRing + sl] = w.ring[i] + (size_t)sl * hd[i].nrhs * hd[i].fbytes;
+    }
+    enum { B_T = 0, B_Q = 1, B_R = 2 };
     int total = 0;
     for (int i = 0; i < nprob; i++) total += probs[i].nrhs;
     std::vector<RhsDesc> rdh(total);
@@ -663,12 +685,16 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
             d.n16 = hd[i].fbytes / 16;
             d.x64 = (char *)probs[i].dst + (size_t)k * spinor_bytes(&probs[i].lat, probs[i].rep, HRD_F64, 1);
             d.r32 = w.f32[i][B_R] + (size_t)k * hd[i].fbytes;
-            d.p32 = w.f32[i][B_P] + (size_t)k * hd[i].fbytes;
-            d.Ap32 = w.f32[i][B_AP] + (size_t)k * hd[i].fbytes;
+            d.p32 = w.ring[i] + (size_t)k * hd[i].fbytes;
+            d.pslot = (size_t)hd[i].nrhs * hd[i].fbytes;
             prob_of[r] = i;
             slot_of[r] = k;
         }
-    std::vector<int> mode(total, M_NORMAL);
+    // mode of each right-hand side, then its first ring slot whose update is
+    // not yet in x (uploaded together)
+    std::vector<int> ml(2 * (size_t)total, 0);
+    int *mode = ml.data();
+    int *lo = ml.data() + total;
     std::vector<double> sc((size_t)S_COUNT * total);
     std::vector<double> bnorm(total), rmax(total), dlt(total, delta);
     std::vector<hrd_cg_info> inf(total);
@@ -702,7 +728,8 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
         return check_hip(hipStreamSynchronize(st), "sync");
     };
     auto upload_mode = [&]() {
-        return check_hip(hipMemcpyAsync(w.mode, mode.data(), sizeof(int) * total, hipMemcpyHostToDevice, st), "mode");
+        return check_hip(hipMemcpyAsync(w.mode, ml.data(), sizeof(int) * 2 * total, hipMemcpyHostToDevice, st),
+                         "mode");
     };
 
     // ||b||^2 and initial residuals
@@ -739,19 +766,23 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
     HRD_TRY(upload_mode());
 
     const dim3 vgrid(kVecBlocks, total);
+    // the right-hand sides step through the ring of search directions in
+    // lockstep: slot j holds the current p of every active one
+    int j = 0;
     int it = 0;
     while (active > 0 && it < maxiter) {
         it++;
-        // q = D^ p (norm partials), alpha; Ap = D^+ q
-        BT(launch_stage(t, false, false, st, w.dd, nprob, ntiles, 1, B_P, B_P, B_T, w.mode, nullptr, 0), "hop");
-        BT(launch_stage(t, false, true, st, w.dd, nprob, ntiles, 0, B_T, B_P, B_Q, w.mode, w.parts, part_stride), "hop");
-        hipLaunchKernelGGL(bcg_alpha_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc);
+        const int P = kBufRing + j;
+        // q = D^ p (norm partials), alpha; r -= alpha D^+ q (norm partials)
+        BT(launch_stage(t, false, false, st, w.dd, nprob, ntiles, 1, P, P, B_T, w.mode, nullptr, 0), "hop");
+        BT(launch_stage(t, false, true, st, w.dd, nprob, ntiles, 0, B_T, P, B_Q, w.mode, w.parts, part_stride), "hop");
+        hipLaunchKernelGGL(bcg_alpha_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc,
+                           w.ahist, j);
         BT(hipGetLastError(), "alpha");
         BT(launch_stage(t, true, false, st, w.dd, nprob, ntiles, 1, B_Q, B_Q, B_T, w.mode, nullptr, 0), "hop");
-        BT(launch_stage(t, true, true, st, w.dd, nprob, ntiles, 0, B_T, B_Q, B_AP, w.mode, w.parts, part_stride), "hop");
-        hipLaunchKernelGGL(bcg_update_r_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, w.vparts);
-        BT(hipGetLastError(), "update r");
-        hipLaunchKernelGGL(bcg_beta_kernel, dim3(total), dim3(256), 0, st, w.mode, w.vparts, w.sc);
+        BT(launch_stage(t, true, true, st, w.dd, nprob, ntiles, 0, B_T, B_Q, B_R, w.mode, w.parts, part_stride, w.sc),
+           "hop, r update");
+        hipLaunchKernelGGL(bcg_beta_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc);
         BT(hipGetLastError(), "beta");
         HRD_TRY(read_sc());
         std::vector<int> reliable;
@@ -773,12 +804,16 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
                 reliable.push_back(r);
             }
         }
+        // normal: p into the next slot (a full ring is folded into x first);
+        // reliable: x brought up to date
+        const int nj = j + 1 < kPRing ? j + 1 : 0;
         HRD_TRY(upload_mode());
-        hipLaunchKernelGGL(bcg_update_xp_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, 0);
-        BT(hipGetLastError(), "update xp");
+        hipLaunchKernelGGL(bcg_ring_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.mode + total, w.sc, w.ahist, j,
+                           nj, nj == 0 ? 1 : 0);
+        BT(hipGetLastError(), "ring");
+        if (nj == 0)
+            for (int r = 0; r < total; r++) lo[r] = 0;
         if (!reliable.empty()) {
-            hipLaunchKernelGGL(bcg_update_xp_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.sc, 1);
-            BT(hipGetLastError(), "update x");
             for (int r : reliable) HRD_TRY(residual(r));
             HRD_TRY(read_sc());
             for (int r : reliable) {
@@ -797,19 +832,30 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
                     // drift of the FP32 recurrence beyond the threshold: restart
                     // p from r and raise this right-hand side's threshold
                     const double rn = inf[r].iterated_rel_residual * bnorm[r];
+                    int bm = kBetaRatio;
                     if (rt > 2.0 * rn) {
                         inf[r].restarts++;
                         dlt[r] = std::min(0.5, 10.0 * dlt[r]);
-                        BT(launch_copy(hd[prob_of[r]].fbytes, rdh[r].r32, rdh[r].p32, st), "p = r");
-                    } else {
-                        BT(launch_cg_update_p32(rdh[r].n16, rdh[r].p32, rdh[r].r32, w.sc + (size_t)r * S_COUNT, st),
-                           "p");
+                        bm = kBetaZero;
                     }
+                    BT(launch_cg_ring(HRD_F32, rdh[r].Vh, rdh[r].ncomp, nullptr, rdh[r].p32, rdh[r].pslot, 0, j, nj,
+                                      rdh[r].r32, w.sc + (size_t)r * S_COUNT, nullptr, bm, st),
+                       "p");
+                    lo[r] = nj;
                     rmax[r] = rt;
                 }
             }
             HRD_TRY(upload_mode());
         }
+        j = nj;
+    }
+    // x of every unfinished right-hand side still lacks the updates of its
+    // slots lo .. j-1
+    if (j > 0) {
+        HRD_TRY(upload_mode());
+        hipLaunchKernelGGL(bcg_ring_kernel, vgrid, dim3(256), 0, st, w.rd, w.mode, w.mode + total, w.sc, w.ahist,
+                           j - 1, -1, 1);
+        BT(hipGetLastError(), "ring flush");
     }
     hrd_status result = HRD_OK;
     for (int r = 0; r < total; r++) {
