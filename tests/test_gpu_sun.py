@@ -129,6 +129,32 @@ def test_cg_sun(oracle, nc, rep, mode):
     assert oracle.true_residual(F.U_orc, b_np, xg, m0) <= 1e-10
 
 
+def test_adjoint_su3_f64_many_blocks(oracle):
+    """SU(3) adjoint (REAL8) FP64 operator on 16x8x8x16 (64 workgroups of the
+    four-lanes-per-site kernel): hop blocks, D^ and their daggers against the
+    oracle, and the FP64 CG (whose second D^+ stage fuses the residual update)
+    to a true residual of 1e-10."""
+    h = hrd()
+    dims, m0 = (16, 8, 8, 16), -0.3
+    F = FieldSUN(dims, 3, "adj", seed=31, kind="smeared")
+    U = F.U_orc
+    psi = F.spinor(32)
+    pe, po = oracle.restrict(psi, 0), oracle.restrict(psi, 1)
+    for dagger in (False, True):
+        hb = oracle.hop_block_dagger if dagger else oracle.hop_block
+        dh = oracle.dhat_dagger if dagger else oracle.dhat
+        for par, x, sites, osites, want in (
+                ("hop_eo", po, "odd", "even", oracle.restrict(hb(U, po, 0), 0)),
+                ("hop_oe", pe, "even", "odd", oracle.restrict(hb(U, pe, 1), 1)),
+                ("eo", pe, "even", "even", dh(U, pe, m0))):
+            out = h.dirac_apply(F.U64, F.pack(x, "f64", sites), m0, F.fmt, par, dims, prec="f64", dagger=dagger)
+            err = rel_err(F.unpack(out, "f64", osites), want)
+            assert err <= 1e-13, (par, dagger, err)
+    x, info = h.cg_solve(F.U64, F.pack(pe, "f64", "even"), m0, 1e-10, dims, F.fmt, mode="f64")
+    assert info["status"] == "HRD_OK"
+    assert oracle.true_residual(U, pe, F.unpack(x, "f64", "even"), m0) <= 1e-10
+
+
 @pytest.mark.parametrize("nc,rep", CASES)
 def test_force_sun(oracle, nc, rep):
     h = hrd()
