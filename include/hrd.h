@@ -45,6 +45,11 @@
  *                   (2k, 2k+1).
  *     link FUND F64: 4 planes of complex128, entries U00, U01, U10, U11.
  *     link FUND F32: 2 planes of 2 x complex64: (U00, U01), (U10, U11).
+ *     FUND F64 and F32 links are stored in TILES of 64 sites: within a block
+ *     (p, mu), sites 64t .. 64t+63 (the last tile: the remaining nb sites)
+ *     hold plane 0 for their nb sites, then plane 1, ...; element (plane q,
+ *     site s) of a block with P planes sits at 16 B x (64t P + q nb + s - 64t),
+ *     t = s / 64.  The block keeps its size, Vh P 16 bytes.
  *     link ADJ  F64: 4 planes of 2 x float64 holding entries (0,1) (2,3) (4,5)
  *                    (6,7), then 1 plane of float64 holding entry 8; entry
  *                    e = 3 a + b of R_ab.

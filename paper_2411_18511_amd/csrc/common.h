@@ -465,6 +465,18 @@ __host__ __device__ constexpr int spinor_site_bytes(int rep, int prec)
     return prec == HRD_F16 ? 4 * ncolour(rep) * 4 + 4 : 4 * ncolour(rep) * (prec == HRD_F64 ? 16 : 8);
 }
 
+// Byte offset of 16-byte plane q of `site` in a block of Vh sites with P
+// planes stored as 64-site tiles: a tile holds the 64 elements (the last
+// tile: the remaining ones) of each of its planes in turn, so a wave's loads
+// of every plane of its links fall into one contiguous stretch instead of P
+// streams.  Used by the FUND link formats.
+__host__ __device__ __forceinline__ size_t tile_off(int Vh, int site, int q, int P)
+{
+    const int b0 = site & ~63;
+    const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
+    return ((size_t)b0 * P + (size_t)q * nb + (size_t)(site - b0)) * 16;
+}
+
 template <>
 struct LinkIO<HRD_FUND, double> {
     using Link = FundLink<double>;
@@ -475,7 +487,7 @@ struct LinkIO<HRD_FUND, double> {
         Link l;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const vd2 v = ld16d<NT>(b + ((size_t)e * Vh + site) * 16);
+            const vd2 v = ld16d<NT>(b + tile_off(Vh, site, e, 4));
             l.u[e >> 1][e & 1] = Cx<double>{v.x, v.y};
         }
         return l;
@@ -485,7 +497,7 @@ struct LinkIO<HRD_FUND, double> {
         char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 64;
 #pragma unroll
         for (int e = 0; e < 4; e++)
-            st16d<false>(b + ((size_t)e * Vh + site) * 16, vd2{l.u[e >> 1][e & 1].re, l.u[e >> 1][e & 1].im});
+            st16d<false>(b + tile_off(Vh, site, e, 4), vd2{l.u[e >> 1][e & 1].re, l.u[e >> 1][e & 1].im});
     }
 };
 
@@ -499,7 +511,7 @@ struct LinkIO<HRD_FUND, float> {
         Link l;
 #pragma unroll
         for (int r = 0; r < 2; r++) {
-            const vf4 v = ld16f<NT>(b + ((size_t)r * Vh + site) * 16);
+            const vf4 v = ld16f<NT>(b + tile_off(Vh, site, r, 2));
             l.u[r][0] = Cx<float>{v.x, v.y};
             l.u[r][1] = Cx<float>{v.z, v.w};
         }
@@ -510,7 +522,7 @@ struct LinkIO<HRD_FUND, float> {
         char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
 #pragma unroll
         for (int r = 0; r < 2; r++)
-            st16f<false>(b + ((size_t)r * Vh + site) * 16, vf4{l.u[r][0].re, l.u[r][0].im, l.u[r][1].re, l.u[r][1].im});
+            st16f<false>(b + tile_off(Vh, site, r, 2), vf4{l.u[r][0].re, l.u[r][0].im, l.u[r][1].re, l.u[r][1].im});
     }
 };
 
