@@ -38,18 +38,23 @@
  *
  * PACKED LAYOUTS ("library layout"; all device memory)
  *   A field of one parity is a sequence of PLANES; a plane is an array of Vh
- *   elements, one per site, in site order.  Spinor components are numbered
- *   k = spin * N + colour (N = 2 FUND, FUND_SU2; 3 ADJ, ADJ_SU2; 4N components).
+ *   elements, one per site, in site order, except where a field is stored in
+ *   TILES (below).  Spinor components are numbered k = spin * N + colour
+ *   (N = 2 FUND, FUND_SU2; 3 ADJ, ADJ_SU2; 4N components).
  *     spinor, F64 : 4N planes of complex128 (16 B): plane k = component k.
  *     spinor, F32 : 2N planes of 2 x complex64 (16 B): plane k = components
  *                   (2k, 2k+1).
  *     link FUND F64: 4 planes of complex128, entries U00, U01, U10, U11.
  *     link FUND F32: 2 planes of 2 x complex64: (U00, U01), (U10, U11).
- *     FUND F64 and F32 links are stored in TILES of 64 sites: within a block
- *     (p, mu), sites 64t .. 64t+63 (the last tile: the remaining nb sites)
- *     hold plane 0 for their nb sites, then plane 1, ...; element (plane q,
- *     site s) of a block with P planes sits at 16 B x (64t P + q nb + s - 64t),
- *     t = s / 64.  The block keeps its size, Vh P 16 bytes.
+ *   TILES (every spinor field, and FUND F64 and F32 links): a block of Vh
+ *     sites (one parity of a spinor, one (parity, mu) of a gauge field) is
+ *     split into tiles of 64 sites (the last tile: the remaining nb sites);
+ *     tile t holds plane 0 of its nb sites, then plane 1, ...; element
+ *     (plane q, site s) of a block with P 16-byte planes sits at byte
+ *     16 (64t P + q nb + s - 64t), t = s / 64.  An F16 spinor tile holds its
+ *     N planes, then the nb FP32 site scales: the scale of site s at byte
+ *     64t (16N + 4) + 16 N nb + 4 (s - 64t), and plane q at
+ *     64t (16N + 4) + 16 (q nb + s - 64t).  Blocks keep their sizes.
  *     link ADJ  F64: 4 planes of 2 x float64 holding entries (0,1) (2,3) (4,5)
  *                    (6,7), then 1 plane of float64 holding entry 8; entry
  *                    e = 3 a + b of R_ab.
@@ -60,7 +65,7 @@
  *     link FUND_SU2, ADJ_SU2 F32: 1 plane of 2 x complex64: (U00, U01).
  *     spinor, F16 : N planes of 16 B, each 4 components as 8 binary16
  *                   (re, im, ...) of the component divided by the site
- *                   scale s, then 1 plane of float32 s (4 B per site).  s is
+ *                   scale s, then the float32 s (4 B per site).  s is
  *                   the largest |re| or |im| over the site's components (after
  *                   rounding them to float32); the stored value is
  *                   binary16(x * (1/s)) in float32 arithmetic, round to

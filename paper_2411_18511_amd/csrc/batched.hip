@@ -287,27 +287,26 @@ __global__ __launch_bounds__(256) void bcg_ring_kernel(const RhsDesc *rd, const 
     const int npl = d.ncomp / 2;
     const long n = (long)npl * d.Vh;
     for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) {
+        const MixOff o = mix_off(t, d.Vh, npl);
         if (flush) {
-            const int q = (int)(t / d.Vh);
-            const int jj = (int)(t - (long)q * d.Vh);
-            double2 *X = reinterpret_cast<double2 *>(d.x64);
-            const size_t i0 = (size_t)(2 * q) * d.Vh + jj, i1 = i0 + d.Vh;
-            double2 x0 = X[i0], x1 = X[i1];
+            double2 *X0 = reinterpret_cast<double2 *>(d.x64 + o.f64a);
+            double2 *X1 = reinterpret_cast<double2 *>(d.x64 + o.f64b);
+            double2 x0 = *X0, x1 = *X1;
             for (int sl = s0; sl <= j; sl++) {
                 const double alpha = al[sl];
-                const float4 pv = reinterpret_cast<const float4 *>(d.p32 + (size_t)sl * d.pslot)[t];
+                const float4 pv = *reinterpret_cast<const float4 *>(d.p32 + (size_t)sl * d.pslot + o.f32);
                 x0.x += alpha * (double)pv.x;
                 x0.y += alpha * (double)pv.y;
                 x1.x += alpha * (double)pv.z;
                 x1.y += alpha * (double)pv.w;
             }
-            X[i0] = x0;
-            X[i1] = x1;
+            *X0 = x0;
+            *X1 = x1;
         }
         if (adv) {
-            const float4 pv = reinterpret_cast<const float4 *>(d.p32 + (size_t)j * d.pslot)[t];
-            const float4 rv = reinterpret_cast<const float4 *>(d.r32)[t];
-            reinterpret_cast<float4 *>(d.p32 + (size_t)dst * d.pslot)[t] =
+            const float4 pv = *reinterpret_cast<const float4 *>(d.p32 + (size_t)j * d.pslot + o.f32);
+            const float4 rv = *reinterpret_cast<const float4 *>(d.r32 + o.f32);
+            *reinterpret_cast<float4 *>(d.p32 + (size_t)dst * d.pslot + o.f32) =
                 make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
         }
     }

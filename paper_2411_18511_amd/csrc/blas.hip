@@ -231,31 +231,30 @@ __global__ __launch_bounds__(kBlock) void cg_ring_f32_kernel(int Vh, int npl, vo
 {
     const long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (long)npl * Vh) return;
+    const MixOff o = mix_off(t, Vh, npl);
     if constexpr ((MODE & 1) != 0) {
-        const int q = (int)(t / Vh);
-        const int j = (int)(t - (long)q * Vh);
-        double2 *X = reinterpret_cast<double2 *>(x64);
-        const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
-        double2 x0 = X[i0], x1 = X[i1];
+        double2 *X0 = reinterpret_cast<double2 *>(static_cast<char *>(x64) + o.f64a);
+        double2 *X1 = reinterpret_cast<double2 *>(static_cast<char *>(x64) + o.f64b);
+        double2 x0 = *X0, x1 = *X1;
 #pragma unroll
         for (int s = 0; s < kPRing; s++) {
             if (s < m) {
                 const double alpha = ahist[s];
-                const float4 pv = reinterpret_cast<const float4 *>(ring + (size_t)s * stride)[t];
+                const float4 pv = *reinterpret_cast<const float4 *>(ring + (size_t)s * stride + o.f32);
                 x0.x += alpha * (double)pv.x;
                 x0.y += alpha * (double)pv.y;
                 x1.x += alpha * (double)pv.z;
                 x1.y += alpha * (double)pv.w;
             }
         }
-        X[i0] = x0;
-        X[i1] = x1;
+        *X0 = x0;
+        *X1 = x1;
     }
     if constexpr ((MODE & 2) != 0) {
         const float beta = ring_beta(sc, beta_mode);
-        const float4 pv = reinterpret_cast<const float4 *>(ring + (size_t)src * stride)[t];
-        const float4 rv = reinterpret_cast<const float4 *>(r32)[t];
-        reinterpret_cast<float4 *>(ring + (size_t)dst * stride)[t] =
+        const float4 pv = *reinterpret_cast<const float4 *>(ring + (size_t)src * stride + o.f32);
+        const float4 rv = *reinterpret_cast<const float4 *>(static_cast<const char *>(r32) + o.f32);
+        *reinterpret_cast<float4 *>(ring + (size_t)dst * stride + o.f32) =
             make_float4(rv.x + beta * pv.x, rv.y + beta * pv.y, rv.z + beta * pv.z, rv.w + beta * pv.w);
     }
 }
@@ -277,18 +276,18 @@ __global__ __launch_bounds__(kRedThreads) void cg_residual_mixed_kernel(int Vh, 
     const long n = (long)npl * Vh;
     double s = 0;
     for (long t = (long)blockIdx.x * kRedThreads + threadIdx.x; t < n; t += (long)gridDim.x * kRedThreads) {
-        const int q = (int)(t / Vh);
-        const int j = (int)(t - (long)q * Vh);
-        const size_t i0 = (size_t)(2 * q) * Vh + j, i1 = i0 + Vh;
-        const double2 b0 = reinterpret_cast<const double2 *>(b)[i0];
-        const double2 b1 = reinterpret_cast<const double2 *>(b)[i1];
-        const double2 a0 = reinterpret_cast<const double2 *>(Ax)[i0];
-        const double2 a1 = reinterpret_cast<const double2 *>(Ax)[i1];
+        const MixOff o = mix_off(t, Vh, npl);
+        auto d2 = [](const void *base, size_t off) {
+            return *reinterpret_cast<const double2 *>(static_cast<const char *>(base) + off);
+        };
+        const double2 b0 = d2(b, o.f64a), b1 = d2(b, o.f64b);
+        const double2 a0 = d2(Ax, o.f64a), a1 = d2(Ax, o.f64b);
         const double2 r0 = make_double2(b0.x - a0.x, b0.y - a0.y);
         const double2 r1 = make_double2(b1.x - a1.x, b1.y - a1.y);
-        reinterpret_cast<double2 *>(r64)[i0] = r0;
-        reinterpret_cast<double2 *>(r64)[i1] = r1;
-        reinterpret_cast<float4 *>(r32)[t] = make_float4((float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y);
+        *reinterpret_cast<double2 *>(static_cast<char *>(r64) + o.f64a) = r0;
+        *reinterpret_cast<double2 *>(static_cast<char *>(r64) + o.f64b) = r1;
+        *reinterpret_cast<float4 *>(static_cast<char *>(r32) + o.f32) =
+            make_float4((float)r0.x, (float)r0.y, (float)r1.x, (float)r1.y);
         s += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
     }
     s = block_sum<kRedThreads>(s);

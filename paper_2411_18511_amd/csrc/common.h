@@ -297,6 +297,42 @@ __device__ __forceinline__ _Float16 to_h16(T x) { return (_Float16)(float)x; }
 // Packed spinor planes: F64 one complex128 per 16-byte element, F32 two
 // complex64 per 16-byte element (components 2k, 2k+1 in plane k).
 // ---------------------------------------------------------------------------
+// 64-site tiles (spinor fields and FUND links): a block of Vh sites (one
+// parity of a spinor, one (parity, direction) of a gauge field) is a sequence
+// of tiles; tile t holds, for its nb sites (64, the last tile the remaining
+// ones), plane 0, then plane 1, ... (16-byte elements), and for F16 spinors
+// then the nb FP32 site scales.  A wave's loads of all planes of its sites
+// thus fall into one contiguous stretch instead of one stream per plane.
+// Byte offset of plane q of `site` in a block of P 16-byte planes and
+// `extra` further bytes per site stored after the planes.
+__host__ __device__ __forceinline__ size_t tile_off(int Vh, int site, int q, int P, int extra = 0)
+{
+    const int b0 = site & ~63;
+    const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
+    return (size_t)b0 * (16 * P + extra) + ((size_t)q * nb + (size_t)(site - b0)) * 16;
+}
+
+// Byte offset of the F16 site scale of `site` (P planes of 16 bytes per site).
+__host__ __device__ __forceinline__ size_t tile_scale_off(int Vh, int site, int P)
+{
+    const int b0 = site & ~63;
+    const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
+    return (size_t)b0 * (16 * P + 4) + (size_t)P * nb * 16 + (size_t)(site - b0) * 4;
+}
+
+// Fields that pair an FP32 spinor (npl planes, components 2q, 2q+1 in plane
+// q) with an FP64 one (2 npl planes): for an index t over (F32 plane q, site
+// j), q slow, the byte offsets of F32 plane q and of F64 planes 2q, 2q+1.
+struct MixOff {
+    size_t f32, f64a, f64b;
+};
+__device__ __forceinline__ MixOff mix_off(long t, int Vh, int npl)
+{
+    const int q = (int)(t / Vh);
+    const int j = (int)(t - (long)q * Vh);
+    return MixOff{tile_off(Vh, j, q, npl), tile_off(Vh, j, 2 * q, 2 * npl), tile_off(Vh, j, 2 * q + 1, 2 * npl)};
+}
+
 template <typename R>
 struct SpinorIO;
 
@@ -308,7 +344,7 @@ struct SpinorIO<double> {
         const char *p = reinterpret_cast<const char *>(base);
 #pragma unroll
         for (int k = 0; k < NC; k++) {
-            const vd2 v = ld16d<NT>(p + ((size_t)k * Vh + site) * 16);
+            const vd2 v = ld16d<NT>(p + tile_off(Vh, site, k, NC));
             c[k] = Cx<double>{v.x, v.y};
         }
     }
@@ -317,7 +353,7 @@ struct SpinorIO<double> {
     {
         char *p = reinterpret_cast<char *>(base);
 #pragma unroll
-        for (int k = 0; k < NC; k++) st16d<NT>(p + ((size_t)k * Vh + site) * 16, vd2{c[k].re, c[k].im});
+        for (int k = 0; k < NC; k++) st16d<NT>(p + tile_off(Vh, site, k, NC), vd2{c[k].re, c[k].im});
     }
 };
 
@@ -329,7 +365,7 @@ struct SpinorIO<float> {
         const char *p = reinterpret_cast<const char *>(base);
 #pragma unroll
         for (int k = 0; k < NC / 2; k++) {
-            const vf4 v = ld16f<NT>(p + ((size_t)k * Vh + site) * 16);
+            const vf4 v = ld16f<NT>(p + tile_off(Vh, site, k, NC / 2));
             c[2 * k] = Cx<float>{v.x, v.y};
             c[2 * k + 1] = Cx<float>{v.z, v.w};
         }
@@ -340,13 +376,14 @@ struct SpinorIO<float> {
         char *p = reinterpret_cast<char *>(base);
 #pragma unroll
         for (int k = 0; k < NC / 2; k++)
-            st16f<NT>(p + ((size_t)k * Vh + site) * 16, vf4{c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im});
+            st16f<NT>(p + tile_off(Vh, site, k, NC / 2),
+                      vf4{c[2 * k].re, c[2 * k].im, c[2 * k + 1].re, c[2 * k + 1].im});
     }
 };
 
 // F16: NC/4 planes of 16-byte elements, each holding four components as eight
-// binary16 (re, im, re, im, ...) divided by the site scale s, followed by one
-// plane of FP32 s (4 bytes per site).  s is the largest |re| or |im| of the
+// binary16 (re, im, re, im, ...) divided by the site scale s, followed in each
+// tile by the FP32 s of its sites (4 bytes per site).  s is the largest |re| or |im| of the
 // site; the stored values are binary16(x * (1/s)) with FP32 x, and a site with
 // s = 0 stores zeros.  Reading gives binary16 * s in FP32.
 template <>
@@ -355,10 +392,10 @@ struct SpinorIO<h16> {
     __device__ __forceinline__ static void load(const void *base, int Vh, int site, Cx<float> (&c)[NC])
     {
         const char *p = reinterpret_cast<const char *>(base);
-        const float s = ld_scalar(reinterpret_cast<const float *>(p + (size_t)(NC / 4) * Vh * 16) + site, NT);
+        const float s = ld_scalar(reinterpret_cast<const float *>(p + tile_scale_off(Vh, site, NC / 4)), NT);
 #pragma unroll
         for (int k = 0; k < NC / 4; k++) {
-            const vh8 v = ld16h<NT>(p + ((size_t)k * Vh + site) * 16);
+            const vh8 v = ld16h<NT>(p + tile_off(Vh, site, k, NC / 4, 4));
 #pragma unroll
             for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<float>{(float)v[2 * j] * s, (float)v[2 * j + 1] * s};
         }
@@ -368,10 +405,10 @@ struct SpinorIO<h16> {
     __device__ __forceinline__ static void load_exact(const void *base, int Vh, int site, Cx<double> (&c)[NC])
     {
         const char *p = reinterpret_cast<const char *>(base);
-        const double s = reinterpret_cast<const float *>(p + (size_t)(NC / 4) * Vh * 16)[site];
+        const double s = *reinterpret_cast<const float *>(p + tile_scale_off(Vh, site, NC / 4));
 #pragma unroll
         for (int k = 0; k < NC / 4; k++) {
-            const vh8 v = ld16h<false>(p + ((size_t)k * Vh + site) * 16);
+            const vh8 v = ld16h<false>(p + tile_off(Vh, site, k, NC / 4, 4));
 #pragma unroll
             for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<double>{(double)v[2 * j] * s, (double)v[2 * j + 1] * s};
         }
@@ -392,9 +429,9 @@ struct SpinorIO<h16> {
                 v[2 * j] = (_Float16)(c[4 * k + j].re * inv);
                 v[2 * j + 1] = (_Float16)(c[4 * k + j].im * inv);
             }
-            st16h<NT>(p + ((size_t)k * Vh + site) * 16, v);
+            st16h<NT>(p + tile_off(Vh, site, k, NC / 4, 4), v);
         }
-        float *sp = reinterpret_cast<float *>(p + (size_t)(NC / 4) * Vh * 16) + site;
+        float *sp = reinterpret_cast<float *>(p + tile_scale_off(Vh, site, NC / 4));
         if constexpr (NT) __builtin_nontemporal_store(m, sp);
         else *sp = m;
     }
@@ -463,18 +500,6 @@ __host__ __device__ constexpr int link_bytes(int rep, int prec)
 __host__ __device__ constexpr int spinor_site_bytes(int rep, int prec)
 {
     return prec == HRD_F16 ? 4 * ncolour(rep) * 4 + 4 : 4 * ncolour(rep) * (prec == HRD_F64 ? 16 : 8);
-}
-
-// Byte offset of 16-byte plane q of `site` in a block of Vh sites with P
-// planes stored as 64-site tiles: a tile holds the 64 elements (the last
-// tile: the remaining ones) of each of its planes in turn, so a wave's loads
-// of every plane of its links fall into one contiguous stretch instead of P
-// streams.  Used by the FUND link formats.
-__host__ __device__ __forceinline__ size_t tile_off(int Vh, int site, int q, int P)
-{
-    const int b0 = site & ~63;
-    const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
-    return ((size_t)b0 * P + (size_t)q * nb + (size_t)(site - b0)) * 16;
 }
 
 template <>

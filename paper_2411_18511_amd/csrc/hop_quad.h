@@ -26,10 +26,9 @@ constexpr int N = 8;           // colours of the representation
 constexpr int kRowPlanes = 4;  // 16-byte planes (two doubles) per link row
 constexpr int kPlanes = 32;    // planes per link
 
-// Loads address a wave-uniform base (plane offset folded in) plus one 32-bit
-// per-lane byte offset, so each load needs no 64-bit address of its own.  One
-// parity of a REAL8 FP64 spinor or link direction then has to stay below
-// 4 GiB (quad_covers).
+// Loads address a wave-uniform base plus a 32-bit per-lane byte offset, so
+// each load needs no 64-bit address of its own.  One parity of a REAL8 FP64
+// spinor or link direction then has to stay below 4 GiB (quad_covers).
 __device__ __forceinline__ Cx<double> ld_c(const char *ubase, uint32_t voff)
 {
     const vd2 v = ld16d<false>(ubase + voff);
@@ -47,6 +46,19 @@ __device__ __forceinline__ void fence(Cx<double> (&v)[M])
 
 __device__ __forceinline__ Cx<double> sel_neg(bool neg, Cx<double> v) { return neg ? -v : v; }
 
+// A site in a 64-site tile of a REAL8 FP64 spinor block (32 planes): byte
+// offset of its plane 0 and the distance between its planes (32-bit; plane q
+// at base + q step, the offsets of tile_off).
+struct SiteOff {
+    uint32_t base, step;
+};
+__device__ __forceinline__ SiteOff site_off(int Vh, int site)
+{
+    const int b0 = site & ~63;
+    const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
+    return SiteOff{(uint32_t)b0 * 512u + (uint32_t)(site - b0) * 16u, (uint32_t)nb * 16u};
+}
+
 // Component k of the upper half spinor of (1 + SIG g_MU) psi (the expressions
 // of project(), with the spin pairing and signs of component k).
 template <int MU, int SIG>
@@ -58,14 +70,14 @@ __device__ __forceinline__ void project_k(const char *src, int Vh, int j, int k,
     if constexpr (MU == 0) neg = SIG < 0;
     else if constexpr (MU == 1) neg = SIG > 0;
     else neg = (k == 0) == (SIG > 0);  // MU 2, 3: component 0 subtracts for SIG > 0
-    const uint32_t vo = ((uint32_t)(k * N) * (uint32_t)Vh + (uint32_t)j) * 16u;
-    const uint32_t vp = ((uint32_t)(par * N) * (uint32_t)Vh + (uint32_t)j) * 16u;
+    const SiteOff so = site_off(Vh, j);
+    const uint32_t vo = so.base + (uint32_t)(k * N) * so.step;
+    const uint32_t vp = so.base + (uint32_t)(par * N) * so.step;
     Cx<double> po[N], pp[N];
 #pragma unroll
     for (int c = 0; c < N; c++) {
-        const char *ub = src + (size_t)c * Vh * 16;
-        po[c] = ld_c(ub, vo);
-        pp[c] = ld_c(ub, vp);
+        po[c] = ld_c(src, vo + (uint32_t)c * so.step);
+        pp[c] = ld_c(src, vp + (uint32_t)c * so.step);
     }
 #pragma unroll
     for (int c = 0; c < N; c++) {
@@ -214,8 +226,9 @@ __global__ __launch_bounds__(kQuadBlock) void hop_quad_kernel(HopArgs a)
         quad_dir<3, DAG>(g, s, idx, p, a.U, a.src, k, hf, up, lo);
         // this lane's planes: spin k and spin 2 + k, colours 4 hf .. 4 hf + 3
         const int pu = k * N + 4 * hf, pl = (2 + k) * N + 4 * hf;
-        const uint32_t vu = ((uint32_t)pu * (uint32_t)g.Vh + (uint32_t)idx) * 16u;
-        const uint32_t vl = ((uint32_t)pl * (uint32_t)g.Vh + (uint32_t)idx) * 16u;
+        const SiteOff si = site_off(g.Vh, idx);
+        const uint32_t vu = si.base + (uint32_t)pu * si.step;
+        const uint32_t vl = si.base + (uint32_t)pl * si.step;
         const double cb = a.b;
         Cx<double> out[8];
 #pragma unroll
@@ -227,9 +240,8 @@ __global__ __launch_bounds__(kQuadBlock) void hop_quad_kernel(HopArgs a)
             const double ca = a.a;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const char *ub = a.self + (size_t)i * g.Vh * 16;
-                out[i] = axpby(ca, ld_c(ub, vu), cb, up[i]);
-                out[4 + i] = axpby(ca, ld_c(ub, vl), cb, lo[i]);
+                out[i] = axpby(ca, ld_c(a.self, vu + (uint32_t)i * si.step), cb, up[i]);
+                out[4 + i] = axpby(ca, ld_c(a.self, vl + (uint32_t)i * si.step), cb, lo[i]);
             }
         }
         char *dst = RUPD ? reinterpret_cast<char *>(a.r) : a.dst;
@@ -237,13 +249,13 @@ __global__ __launch_bounds__(kQuadBlock) void hop_quad_kernel(HopArgs a)
             const double alpha = a.sc[S_ALPHA];
 #pragma unroll
             for (int i = 0; i < 8; i++) {
-                const Cx<double> rv = ld_c(dst + (size_t)(i & 3) * g.Vh * 16, i < 4 ? vu : vl);
+                const Cx<double> rv = ld_c(dst, (i < 4 ? vu : vl) + (uint32_t)(i & 3) * si.step);
                 out[i] = Cx<double>{fmadd(-alpha, out[i].re, rv.re), fmadd(-alpha, out[i].im, rv.im)};
             }
         }
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            st16d<HRD_NT_STORE>(dst + (size_t)(i & 3) * g.Vh * 16 + (i < 4 ? vu : vl), vd2{out[i].re, out[i].im});
+            st16d<HRD_NT_STORE>(dst + ((i < 4 ? vu : vl) + (uint32_t)(i & 3) * si.step), vd2{out[i].re, out[i].im});
             if constexpr (NORM || RUPD) nrm += out[i].re * out[i].re + out[i].im * out[i].im;
         }
     }

@@ -275,20 +275,19 @@ __global__ __launch_bounds__(kBlock) void convert_spinor_kernel(int Vh, int npar
     if (t >= (long)nparity * npl * Vh) return;
     const int blk = (int)(t / ((long)npl * Vh));
     const long r = t - (long)blk * npl * Vh;
-    const int q = (int)(r / Vh);
-    const int j = (int)(r - (long)q * Vh);
-    const size_t base64 = (size_t)blk * ncomp * Vh;  // in double2 units
-    const size_t base32 = (size_t)blk * npl * Vh;    // in float4 units
-    double2 *d = reinterpret_cast<double2 *>(to_f32 ? const_cast<void *>(in) : out);
-    float4 *f = reinterpret_cast<float4 *>(to_f32 ? out : const_cast<void *>(in));
+    const MixOff o = mix_off(r, Vh, npl);
+    char *d = static_cast<char *>(to_f32 ? const_cast<void *>(in) : out) + (size_t)blk * ncomp * Vh * 16;
+    char *f = static_cast<char *>(to_f32 ? out : const_cast<void *>(in)) + (size_t)blk * npl * Vh * 16;
+    double2 *d0 = reinterpret_cast<double2 *>(d + o.f64a);
+    double2 *d1 = reinterpret_cast<double2 *>(d + o.f64b);
+    float4 *fv = reinterpret_cast<float4 *>(f + o.f32);
     if (to_f32) {
-        const double2 a = d[base64 + (size_t)(2 * q) * Vh + j];
-        const double2 b = d[base64 + (size_t)(2 * q + 1) * Vh + j];
-        f[base32 + (size_t)q * Vh + j] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+        const double2 a = *d0, b = *d1;
+        *fv = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
     } else {
-        const float4 v = f[base32 + (size_t)q * Vh + j];
-        d[base64 + (size_t)(2 * q) * Vh + j] = make_double2(v.x, v.y);
-        d[base64 + (size_t)(2 * q + 1) * Vh + j] = make_double2(v.z, v.w);
+        const float4 v = *fv;
+        *d0 = make_double2(v.x, v.y);
+        *d1 = make_double2(v.z, v.w);
     }
 }
 

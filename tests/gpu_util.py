@@ -40,6 +40,17 @@ def from_dev_gauge(t, dims):
     return t.cpu().numpy().reshape((4,) + tuple(dims) + tuple(t.shape[-2:]))
 
 
+def tile_index(Vh, site, q, P):
+    """Position, in 16-byte elements, of plane q of `site` in a block of Vh
+    sites with P planes stored in 64-site tiles (the layout include/hrd.h
+    documents): tile t = site // 64 holds plane 0 of its nb sites, then plane
+    1, ...; nb = 64 except in the last tile."""
+    site = np.asarray(site)
+    b0 = site & ~63
+    nb = np.minimum(64, Vh - b0)
+    return b0 * P + q * nb + (site - b0)
+
+
 def rel_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 

@@ -39,19 +39,26 @@ def parity_sites(dims, p, oracle):
 
 
 def decode_spinor16(raw, dims, n, nparity):
-    """Host decoder of the documented F16 spinor layout: returns (codes [nparity, Vh, 4, n, 2] float16,
-    scales [nparity, Vh] float32)."""
+    """Host decoder of the documented F16 spinor layout (64-site tiles of N
+    planes followed by the tile's FP32 site scales): returns (codes
+    [nparity, Vh, 4, n, 2] float16, scales [nparity, Vh] float32)."""
     Vh = int(np.prod(dims)) // 2
     nc = 4 * n
+    P = nc // 4
     blk = Vh * (4 * nc + 4)
     b = raw.cpu().numpy().view(np.uint8)
+    site = np.arange(Vh)
+    b0 = site & ~63
+    nb = np.minimum(64, Vh - b0)
+    tile = b0 * (16 * P + 4)  # byte offset of each site's 64-site tile
     codes, scales = [], []
     for q in range(nparity):
         part = b[q * blk:(q + 1) * blk]
-        planes = part[: Vh * 16 * (nc // 4)].view(np.float16).reshape(nc // 4, Vh, 8)
-        c = planes.transpose(1, 0, 2).reshape(Vh, nc, 2).reshape(Vh, 4, n, 2)
+        planes = np.stack([part[(tile + (k * nb + site - b0) * 16)[:, None] + np.arange(16)] for k in range(P)])
+        c = planes.view(np.float16).reshape(P, Vh, 8).transpose(1, 0, 2).reshape(Vh, nc, 2).reshape(Vh, 4, n, 2)
         codes.append(c)
-        scales.append(part[Vh * 16 * (nc // 4):].view(np.float32))
+        sc = part[(tile + P * nb * 16 + (site - b0) * 4)[:, None] + np.arange(4)]
+        scales.append(sc.view(np.float32).reshape(Vh))
     return np.stack(codes), np.stack(scales)
 
 

@@ -12,7 +12,7 @@ narrower than L1 (the traversal used at 48^4).
 import numpy as np
 import pytest
 
-from gpu_util import Field, from_dev_gauge, requires_gpu, rel_err, hrd
+from gpu_util import tile_index, Field, from_dev_gauge, requires_gpu, rel_err, hrd
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -81,20 +81,22 @@ def test_pack_round_trip_and_layout(dims, rep):
         else:
             par = 0 if sites == "even" else 1
             assert np.array_equal(back, O.restrict(psi, par))
-    # documented layout: F64 full field [parity][component][Vh], index lex >> 1
+    # documented layout: F64 full field [parity][64-site tiles of component
+    # planes], site index lex >> 1
     packed = F.pack(psi, "f64", "all").cpu().numpy().view(np.complex128)
     V = int(np.prod(dims))
+    Vh = V // 2
     NC = 4 * F.n
     flat = psi.reshape(V, NC)
     t, x1, x2, x3 = np.unravel_index(np.arange(V), dims)
     par = (t + x1 + x2 + x3) % 2
     idx = np.arange(V) >> 1
     for k in range(NC):
-        assert np.array_equal(packed[(par * NC + k) * (V // 2) + idx], flat[:, k])
-    # F32: planes of component pairs
+        assert np.array_equal(packed[par * NC * Vh + tile_index(Vh, idx, k, NC)], flat[:, k])
+    # F32: planes of component pairs, same tiles
     p32 = F.pack(psi, "f32", "all").cpu().numpy().view(np.complex64)
     for k in range(NC):
-        pos = ((par * (NC // 2) + k // 2) * (V // 2) + idx) * 2 + (k % 2)
+        pos = (par * (NC // 2) * Vh + tile_index(Vh, idx, k // 2, NC // 2)) * 2 + (k % 2)
         assert np.array_equal(p32[pos], flat[:, k].astype(np.complex64))
     # gauge round trip
     if rep == "fund":
