@@ -46,7 +46,8 @@
  *                   (2k, 2k+1).
  *     link FUND F64: 4 planes of complex128, entries U00, U01, U10, U11.
  *     link FUND F32: 2 planes of 2 x complex64: (U00, U01), (U10, U11).
- *   TILES (every spinor field, and FUND F64 and F32 links): a block of Vh
+ *   TILES (every spinor field, FUND F64 and F32 links, and FUND_SU2 and
+ *     ADJ_SU2 F64 links; the other link layouts are planes): a block of Vh
  *     sites (one parity of a spinor, one (parity, mu) of a gauge field) is
  *     split into tiles of 64 sites (the last tile: the remaining nb sites);
  *     tile t holds plane 0 of its nb sites, then plane 1, ...; element

@@ -297,7 +297,7 @@ __device__ __forceinline__ _Float16 to_h16(T x) { return (_Float16)(float)x; }
 // Packed spinor planes: F64 one complex128 per 16-byte element, F32 two
 // complex64 per 16-byte element (components 2k, 2k+1 in plane k).
 // ---------------------------------------------------------------------------
-// 64-site tiles (spinor fields and FUND links): a block of Vh sites (one
+// 64-site tiles (spinor fields, FUND links and FP64 first-row SU(2) links): a block of Vh sites (one
 // parity of a spinor, one (parity, direction) of a gauge field) is a sequence
 // of tiles; tile t holds, for its nb sites (64, the last tile the remaining
 // ones), plane 0, then plane 1, ... (16-byte elements), and for F16 spinors
@@ -639,15 +639,15 @@ struct RowIO<double> {
     __device__ __forceinline__ static Su2Row<double> load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
-        const vd2 x = ld16d<NT>(b + (size_t)site * 16);
-        const vd2 y = ld16d<NT>(b + ((size_t)Vh + site) * 16);
+        const vd2 x = ld16d<NT>(b + tile_off(Vh, site, 0, 2));
+        const vd2 y = ld16d<NT>(b + tile_off(Vh, site, 1, 2));
         return Su2Row<double>{{x.x, x.y}, {y.x, y.y}};
     }
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Su2Row<double> &r)
     {
         char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 32;
-        st16d<false>(b + (size_t)site * 16, vd2{r.a.re, r.a.im});
-        st16d<false>(b + ((size_t)Vh + site) * 16, vd2{r.b.re, r.b.im});
+        st16d<false>(b + tile_off(Vh, site, 0, 2), vd2{r.a.re, r.a.im});
+        st16d<false>(b + tile_off(Vh, site, 1, 2), vd2{r.b.re, r.b.im});
     }
 };
 

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import Field, from_dev_gauge, requires_gpu, rel_err, hrd
+from gpu_util import tile_index, Field, from_dev_gauge, requires_gpu, rel_err, hrd
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -69,8 +69,8 @@ def test_su2_layout_and_round_trip():
     idx = np.arange(V) >> 1
     for mu in range(4):
         flat = F.Uf[mu].reshape(V, 2, 2)
-        for e in range(2):
-            assert np.array_equal(packed[((par * 4 + mu) * 2 + e) * Vh + idx], flat[:, 0, e])
+        for e in range(2):  # 64-site tiles of the two planes (U00, U01)
+            assert np.array_equal(packed[(par * 4 + mu) * 2 * Vh + tile_index(Vh, idx, e, 2)], flat[:, 0, e])
 
 
 @pytest.mark.parametrize("rep,m0", [("fund_su2", -0.3), ("adj_su2", -0.5)])
