@@ -297,11 +297,11 @@ __device__ __forceinline__ _Float16 to_h16(T x) { return (_Float16)(float)x; }
 // Packed spinor planes: F64 one complex128 per 16-byte element, F32 two
 // complex64 per 16-byte element (components 2k, 2k+1 in plane k).
 // ---------------------------------------------------------------------------
-// 64-site tiles (spinor fields, FUND links and FP64 first-row SU(2) links): a block of Vh sites (one
+// 64-site tiles (spinor fields, FUND and ADJ links, FP64 first-row SU(2) links): a block of Vh sites (one
 // parity of a spinor, one (parity, direction) of a gauge field) is a sequence
 // of tiles; tile t holds, for its nb sites (64, the last tile the remaining
 // ones), plane 0, then plane 1, ... (16-byte elements), and for F16 spinors
-// then the nb FP32 site scales.  A wave's loads of all planes of its sites
+// then the nb FP32 site scales (ADJ links: the nb last entries).  A wave's loads of all planes of its sites
 // thus fall into one contiguous stretch instead of one stream per plane.
 // Byte offset of plane q of `site` in a block of P 16-byte planes and
 // `extra` further bytes per site stored after the planes.
@@ -312,12 +312,17 @@ __host__ __device__ __forceinline__ size_t tile_off(int Vh, int site, int q, int
     return (size_t)b0 * (16 * P + extra) + ((size_t)q * nb + (size_t)(site - b0)) * 16;
 }
 
-// Byte offset of the F16 site scale of `site` (P planes of 16 bytes per site).
-__host__ __device__ __forceinline__ size_t tile_scale_off(int Vh, int site, int P)
+// Byte offset of the trailing E-byte element of `site` (after P planes of 16
+// bytes per site): the F16 spinor scale (E = 4), the last ADJ link entry.
+__host__ __device__ __forceinline__ size_t tile_extra_off(int Vh, int site, int P, int E)
 {
     const int b0 = site & ~63;
     const int nb = Vh - b0 < 64 ? Vh - b0 : 64;
-    return (size_t)b0 * (16 * P + 4) + (size_t)P * nb * 16 + (size_t)(site - b0) * 4;
+    return (size_t)b0 * (16 * P + E) + (size_t)P * nb * 16 + (size_t)(site - b0) * E;
+}
+__host__ __device__ __forceinline__ size_t tile_scale_off(int Vh, int site, int P)
+{
+    return tile_extra_off(Vh, site, P, 4);
 }
 
 // Fields that pair an FP32 spinor (npl planes, components 2q, 2q+1 in plane
@@ -558,16 +563,16 @@ struct LinkIO<HRD_ADJ, double> {
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 72;
-        const double *b1 = reinterpret_cast<const double *>(blk + (size_t)Vh * 64);
+        const double *b1 = reinterpret_cast<const double *>(blk + tile_extra_off(Vh, site, 4, 8));
         double e[9];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const vd2 v = ld16d<NT>(blk + ((size_t)k * Vh + site) * 16);
+            const vd2 v = ld16d<NT>(blk + tile_off(Vh, site, k, 4, 8));
             e[2 * k] = v.x;
             e[2 * k + 1] = v.y;
         }
-        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1 + site);
-        else e[8] = b1[site];
+        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1);
+        else e[8] = *b1;
         Link l;
 #pragma unroll
         for (int k = 0; k < 9; k++) l.r[k / 3][k % 3] = e[k];
@@ -576,13 +581,13 @@ struct LinkIO<HRD_ADJ, double> {
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
         char *blk = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 72;
-        double *b1 = reinterpret_cast<double *>(blk + (size_t)Vh * 64);
+        double *b1 = reinterpret_cast<double *>(blk + tile_extra_off(Vh, site, 4, 8));
         double e[9];
 #pragma unroll
         for (int k = 0; k < 9; k++) e[k] = l.r[k / 3][k % 3];
 #pragma unroll
-        for (int k = 0; k < 4; k++) st16d<false>(blk + ((size_t)k * Vh + site) * 16, vd2{e[2 * k], e[2 * k + 1]});
-        b1[site] = e[8];
+        for (int k = 0; k < 4; k++) st16d<false>(blk + tile_off(Vh, site, k, 4, 8), vd2{e[2 * k], e[2 * k + 1]});
+        *b1 = e[8];
     }
 };
 
@@ -593,18 +598,18 @@ struct LinkIO<HRD_ADJ, float> {
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 36;
-        const float *b1 = reinterpret_cast<const float *>(blk + (size_t)Vh * 32);
+        const float *b1 = reinterpret_cast<const float *>(blk + tile_extra_off(Vh, site, 2, 4));
         float e[9];
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-            const vf4 v = ld16f<NT>(blk + ((size_t)k * Vh + site) * 16);
+            const vf4 v = ld16f<NT>(blk + tile_off(Vh, site, k, 2, 4));
             e[4 * k] = v.x;
             e[4 * k + 1] = v.y;
             e[4 * k + 2] = v.z;
             e[4 * k + 3] = v.w;
         }
-        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1 + site);
-        else e[8] = b1[site];
+        if constexpr (NT) e[8] = __builtin_nontemporal_load(b1);
+        else e[8] = *b1;
         Link l;
 #pragma unroll
         for (int k = 0; k < 9; k++) l.r[k / 3][k % 3] = e[k];
@@ -613,14 +618,14 @@ struct LinkIO<HRD_ADJ, float> {
     __device__ __forceinline__ static void store(void *U, int Vh, int p, int mu, int site, const Link &l)
     {
         char *blk = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * 36;
-        float *b1 = reinterpret_cast<float *>(blk + (size_t)Vh * 32);
+        float *b1 = reinterpret_cast<float *>(blk + tile_extra_off(Vh, site, 2, 4));
         float e[9];
 #pragma unroll
         for (int k = 0; k < 9; k++) e[k] = l.r[k / 3][k % 3];
 #pragma unroll
         for (int k = 0; k < 2; k++)
-            st16f<false>(blk + ((size_t)k * Vh + site) * 16, vf4{e[4 * k], e[4 * k + 1], e[4 * k + 2], e[4 * k + 3]});
-        b1[site] = e[8];
+            st16f<false>(blk + tile_off(Vh, site, k, 2, 4), vf4{e[4 * k], e[4 * k + 1], e[4 * k + 2], e[4 * k + 3]});
+        *b1 = e[8];
     }
 };
 
@@ -705,8 +710,8 @@ struct LinkIO<HRD_ADJ, h16> {
     __device__ __forceinline__ static Link load(const void *U, int Vh, int p, int mu, int site)
     {
         const char *blk = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * 18;
-        const vh8 v = ld16h<NT>(blk + (size_t)site * 16);
-        const _Float16 e8 = ld_scalar(reinterpret_cast<const _Float16 *>(blk + (size_t)Vh * 16) + site, NT);
+        const vh8 v = ld16h<NT>(blk + tile_off(Vh, site, 0, 1, 2));
+        const _Float16 e8 = ld_scalar(reinterpret_cast<const _Float16 *>(blk + tile_extra_off(Vh, site, 1, 2)), NT);
         Link l;
 #pragma unroll
         for (int k = 0; k < 8; k++) l.r[k / 3][k % 3] = (float)v[k];
@@ -720,8 +725,8 @@ struct LinkIO<HRD_ADJ, h16> {
         vh8 v;
 #pragma unroll
         for (int k = 0; k < 8; k++) v[k] = to_h16(l.r[k / 3][k % 3]);
-        st16h<false>(blk + (size_t)site * 16, v);
-        reinterpret_cast<_Float16 *>(blk + (size_t)Vh * 16)[site] = to_h16(l.r[2][2]);
+        st16h<false>(blk + tile_off(Vh, site, 0, 1, 2), v);
+        *reinterpret_cast<_Float16 *>(blk + tile_extra_off(Vh, site, 1, 2)) = to_h16(l.r[2][2]);
     }
 };
 

@@ -98,10 +98,14 @@ def decode_links16(raw, dims, rep):
         elif rep == "fund":
             blk = b[pm * Vh * 16:(pm + 1) * Vh * 16].view(np.float16).reshape(Vh, 8)
             out.append(blk.astype(np.float64))
-        else:
+        else:  # 64-site tiles: the tile's 16-byte planes, then its entries 8
             blk = b[pm * Vh * 18:(pm + 1) * Vh * 18]
-            e = blk[: Vh * 16].view(np.float16).reshape(Vh, 8)
-            e8 = blk[Vh * 16:].view(np.float16).reshape(Vh, 1)
+            site = np.arange(Vh)
+            b0 = site & ~63
+            nb = np.minimum(64, Vh - b0)
+            tile = b0 * 18
+            e = blk[(tile + (site - b0) * 16)[:, None] + np.arange(16)].view(np.float16).reshape(Vh, 8)
+            e8 = blk[(tile + nb * 16 + (site - b0) * 2)[:, None] + np.arange(2)].view(np.float16).reshape(Vh, 1)
             out.append(np.concatenate([e, e8], axis=1).astype(np.float64))
     return out
 
