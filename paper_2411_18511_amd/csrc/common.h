@@ -396,14 +396,21 @@ struct SpinorIO<h16> {
     template <int NC, bool NT = false>
     __device__ __forceinline__ static void load(const void *base, int Vh, int site, Cx<float> (&c)[NC])
     {
-        const char *p = reinterpret_cast<const char *>(base);
-        const float s = ld_scalar(reinterpret_cast<const float *>(p + tile_scale_off(Vh, site, NC / 4)), NT);
+        // plane 0 of the site and the distance between planes, computed once;
+        // all planes and the scale are loaded before any is converted
+        constexpr int P = NC / 4;
+        const int b0 = site & ~63, off = site - b0;
+        const size_t step = (size_t)(Vh - b0 < 64 ? Vh - b0 : 64) * 16;  // nb 16-byte elements
+        const char *tile = reinterpret_cast<const char *>(base) + (size_t)b0 * (16 * P + 4);
+        const char *p0 = tile + (size_t)off * 16;
+        vh8 v[P];
 #pragma unroll
-        for (int k = 0; k < NC / 4; k++) {
-            const vh8 v = ld16h<NT>(p + tile_off(Vh, site, k, NC / 4, 4));
+        for (int k = 0; k < P; k++) v[k] = ld16h<NT>(p0 + k * step);
+        const float s = ld_scalar(reinterpret_cast<const float *>(tile + P * step + (size_t)off * 4), NT);
 #pragma unroll
-            for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<float>{(float)v[2 * j] * s, (float)v[2 * j + 1] * s};
-        }
+        for (int k = 0; k < P; k++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) c[4 * k + j] = Cx<float>{(float)v[k][2 * j] * s, (float)v[k][2 * j + 1] * s};
     }
     // the stored value exactly (binary16 * s in FP64), for conversions to F64
     template <int NC>

@@ -200,8 +200,19 @@ __device__ __forceinline__ void dense_mul_dag_rows(const void *U, int Vh, int p,
     }
 }
 
+// Dense links of at most 64 bytes (CPLX3 and CPLX4 in F16) are loaded whole
+// and multiplied from registers (link_mul: the same operations in the same
+// order as the row-streamed products), so their few loads are issued
+// together.
+template <int REP, typename S>
+constexpr bool dense_whole_link()
+{
+    constexpr int prec = std::is_same<S, double>::value ? HRD_F64 : std::is_same<S, float>::value ? HRD_F32 : HRD_F16;
+    return is_dense(REP) && !is_real_dense(REP) && REP != HRD_SU3_ROW2 && link_bytes(REP, prec) <= 64;
+}
+
 // One direction of the stencil for the dense formats (same arithmetic as
-// hop_dir, links streamed by row).
+// hop_dir, links streamed by row or, for small links, loaded whole).
 template <int MU, bool DAG, int REP, typename S, typename R = typename Arith<S>::type>
 __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int idx, int p, const void *U,
                                               const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
@@ -226,7 +237,13 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
                 h1[c] = -h1[c];
             }
         }
-        dense_mul_rows<REP, S, 0, N, R>(U, g.Vh, p, MU, idx, h0, h1, u0, u1);
+        if constexpr (dense_whole_link<REP, S>()) {
+            const auto l = LinkIO<REP, S>::template load<HRD_NT_LINKS>(U, g.Vh, p, MU, idx);
+            link_mul(l, h0, u0);
+            link_mul(l, h1, u1);
+        } else {
+            dense_mul_rows<REP, S, 0, N, R>(U, g.Vh, p, MU, idx, h0, h1, u0, u1);
+        }
         reconstruct<MU, SF, N, R>(acc, u0, u1);
     }
     dir_fence(acc);
@@ -245,7 +262,13 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
                 h1[c] = -h1[c];
             }
         }
-        dense_mul_dag_rows<REP, S, 0, N, R>(U, g.Vh, 1 - p, MU, j, h0, h1, u0, u1);
+        if constexpr (dense_whole_link<REP, S>()) {
+            const auto l = LinkIO<REP, S>::template load<HRD_NT_LINKS>(U, g.Vh, 1 - p, MU, j);
+            link_mul_dag(l, h0, u0);
+            link_mul_dag(l, h1, u1);
+        } else {
+            dense_mul_dag_rows<REP, S, 0, N, R>(U, g.Vh, 1 - p, MU, j, h0, h1, u0, u1);
+        }
         reconstruct<MU, SB, N, R>(acc, u0, u1);
     }
     dir_fence(acc);
