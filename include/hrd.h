@@ -46,8 +46,9 @@
  *                   (2k, 2k+1).
  *     link FUND F64: 4 planes of complex128, entries U00, U01, U10, U11.
  *     link FUND F32: 2 planes of 2 x complex64: (U00, U01), (U10, U11).
- *   TILES (every spinor and gauge field; for a field of a single plane the
- *     tiles are that plane): a block of Vh
+ *   TILES (every spinor field, FUND F64 and F32 links, ADJ links, and
+ *     FUND_SU2 and ADJ_SU2 F64 links; the other link layouts are planes):
+ *     a block of Vh
  *     sites (one parity of a spinor, one (parity, mu) of a gauge field) is
  *     split into tiles of 64 sites (the last tile: the remaining nb sites);
  *     tile t holds plane 0 of its nb sites, then plane 1, ...; element
@@ -59,9 +60,7 @@
  *     its 16-byte planes, then the nb last entries (entry 8: float64,
  *     float32 or binary16): with P planes and E-byte entries, plane q of
  *     site s at 64t (16P + E) + 16 (q nb + s - 64t), entry 8 at
- *     64t (16P + E) + 16 P nb + E (s - 64t); an F16 SU3_ROW2 tile holds
- *     its 16-byte plane, then the 8-byte (U11, U12) of its sites.  Blocks
- *     keep their sizes.
+ *     64t (16P + E) + 16 P nb + E (s - 64t).  Blocks keep their sizes.
  *     link ADJ  F64: 4 planes of 2 x float64 holding entries (0,1) (2,3) (4,5)
  *                    (6,7), then 1 plane of float64 holding entry 8; entry
  *                    e = 3 a + b of R_ab.

@@ -297,8 +297,7 @@ __device__ __forceinline__ _Float16 to_h16(T x) { return (_Float16)(float)x; }
 // Packed spinor planes: F64 one complex128 per 16-byte element, F32 two
 // complex64 per 16-byte element (components 2k, 2k+1 in plane k).
 // ---------------------------------------------------------------------------
-// 64-site tiles (every spinor and link field; for a single plane the tiles
-// are the plane): a block of Vh sites (one
+// 64-site tiles (spinor fields, FUND and ADJ links, FP64 first-row SU(2) links): a block of Vh sites (one
 // parity of a spinor, one (parity, direction) of a gauge field) is a sequence
 // of tiles; tile t holds, for its nb sites (64, the last tile the remaining
 // ones), plane 0, then plane 1, ... (16-byte elements), and for F16 spinors
@@ -835,7 +834,7 @@ struct CplxIO<N, double> {
         const char *b = reinterpret_cast<const char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
 #pragma unroll
         for (int j = 0; j < N; j++) {
-            const vd2 v = ld16d<NT>(b + tile_off(Vh, site, N * I + j, kPlanes));
+            const vd2 v = ld16d<NT>(b + ((size_t)(N * I + j) * Vh + site) * 16);
             row[j] = Cx<double>{v.x, v.y};
         }
     }
@@ -846,7 +845,7 @@ struct CplxIO<N, double> {
         Link l;
 #pragma unroll
         for (int e = 0; e < N * N; e++) {
-            const vd2 v = ld16d<NT>(b + tile_off(Vh, site, e, kPlanes));
+            const vd2 v = ld16d<NT>(b + ((size_t)e * Vh + site) * 16);
             l.u[e / N][e % N] = Cx<double>{v.x, v.y};
         }
         return l;
@@ -857,7 +856,7 @@ struct CplxIO<N, double> {
         char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
 #pragma unroll
         for (int e = 0; e < N * N; e++)
-            st16d<false>(b + tile_off(Vh, site, e, kPlanes), vd2{(double)l.u[e / N][e % N].re, (double)l.u[e / N][e % N].im});
+            st16d<false>(b + ((size_t)e * Vh + site) * 16, vd2{(double)l.u[e / N][e % N].re, (double)l.u[e / N][e % N].im});
     }
 };
 
@@ -872,7 +871,7 @@ struct CplxIO<N, float> {
         constexpr int e0 = N * I, e1 = N * I + N;
 #pragma unroll
         for (int q = e0 / 2; q <= (e1 - 1) / 2; q++) {
-            const vf4 v = ld16f<NT>(b + tile_off(Vh, site, q, kPlanes));
+            const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
             if (2 * q >= e0) row[2 * q - e0] = Cx<float>{v.x, v.y};
             if (2 * q + 1 < e1) row[2 * q + 1 - e0] = Cx<float>{v.z, v.w};
         }
@@ -884,7 +883,7 @@ struct CplxIO<N, float> {
         Link l;
 #pragma unroll
         for (int q = 0; q < kPlanes; q++) {
-            const vf4 v = ld16f<NT>(b + tile_off(Vh, site, q, kPlanes));
+            const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
             l.u[(2 * q) / N][(2 * q) % N] = Cx<float>{v.x, v.y};
             if (2 * q + 1 < N * N) l.u[(2 * q + 1) / N][(2 * q + 1) % N] = Cx<float>{v.z, v.w};
         }
@@ -899,7 +898,7 @@ struct CplxIO<N, float> {
             const int e0 = 2 * q, e1 = 2 * q + 1;
             const Cx<T> a = l.u[e0 / N][e0 % N];
             const Cx<T> c = e1 < N * N ? l.u[e1 / N][e1 % N] : Cx<T>{0, 0};
-            st16f<false>(b + tile_off(Vh, site, q, kPlanes), vf4{(float)a.re, (float)a.im, (float)c.re, (float)c.im});
+            st16f<false>(b + ((size_t)q * Vh + site) * 16, vf4{(float)a.re, (float)a.im, (float)c.re, (float)c.im});
         }
     }
 };
@@ -915,7 +914,7 @@ struct CplxIO<N, h16> {
         constexpr int e0 = N * I, e1 = N * I + N;
 #pragma unroll
         for (int q = e0 / 4; q <= (e1 - 1) / 4; q++) {
-            const vh8 v = ld16h<NT>(b + tile_off(Vh, site, q, kPlanes));
+            const vh8 v = ld16h<NT>(b + ((size_t)q * Vh + site) * 16);
 #pragma unroll
             for (int j = 0; j < 4; j++)
                 if (4 * q + j >= e0 && 4 * q + j < e1)
@@ -929,7 +928,7 @@ struct CplxIO<N, h16> {
         Link l;
 #pragma unroll
         for (int q = 0; q < kPlanes; q++) {
-            const vh8 v = ld16h<NT>(b + tile_off(Vh, site, q, kPlanes));
+            const vh8 v = ld16h<NT>(b + ((size_t)q * Vh + site) * 16);
 #pragma unroll
             for (int j = 0; j < 4; j++)
                 if (4 * q + j < N * N)
@@ -951,7 +950,7 @@ struct CplxIO<N, h16> {
                 v[2 * j] = to_h16(a.re);
                 v[2 * j + 1] = to_h16(a.im);
             }
-            st16h<false>(b + tile_off(Vh, site, q, kPlanes), v);
+            st16h<false>(b + ((size_t)q * Vh + site) * 16, v);
         }
     }
 };
@@ -970,7 +969,7 @@ struct RealIO {
         constexpr int e0 = N * I, e1 = N * I + N;
 #pragma unroll
         for (int q = e0 / kPer; q <= (e1 - 1) / kPer; q++) {
-            const char *a = b + tile_off(Vh, site, q, kPlanes);
+            const char *a = b + ((size_t)q * Vh + site) * 16;
             A e[kPer];
             if constexpr (kPer == 2) {
                 const vd2 v = ld16d<NT>(a);
@@ -999,7 +998,7 @@ struct RealIO {
         Link l;
 #pragma unroll
         for (int q = 0; q < kPlanes; q++) {
-            const char *a = b + tile_off(Vh, site, q, kPlanes);
+            const char *a = b + ((size_t)q * Vh + site) * 16;
             A e[kPer];
             if constexpr (kPer == 2) {
                 const vd2 v = ld16d<NT>(a);
@@ -1028,7 +1027,7 @@ struct RealIO {
         char *b = reinterpret_cast<char *>(U) + (size_t)(4 * p + mu) * Vh * kPlanes * 16;
 #pragma unroll
         for (int q = 0; q < kPlanes; q++) {
-            char *a = b + tile_off(Vh, site, q, kPlanes);
+            char *a = b + ((size_t)q * Vh + site) * 16;
             T e[kPer];
 #pragma unroll
             for (int j = 0; j < kPer; j++) {
@@ -1066,19 +1065,19 @@ struct LinkIO<HRD_SU3_ROW2, S> {
         if constexpr (std::is_same<S, double>::value) {
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                const vd2 v = ld16d<NT>(b + tile_off(Vh, site, k, 6));
+                const vd2 v = ld16d<NT>(b + ((size_t)k * Vh + site) * 16);
                 e[k] = Cx<A>{v.x, v.y};
             }
         } else if constexpr (std::is_same<S, float>::value) {
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                const vf4 v = ld16f<NT>(b + tile_off(Vh, site, q, 3));
+                const vf4 v = ld16f<NT>(b + ((size_t)q * Vh + site) * 16);
                 e[2 * q] = Cx<A>{v.x, v.y};
                 e[2 * q + 1] = Cx<A>{v.z, v.w};
             }
         } else {
-            const vh8 v = ld16h<NT>(b + tile_off(Vh, site, 0, 1, 8));
-            const vh4 w = ld8h<NT>(b + tile_extra_off(Vh, site, 1, 8));
+            const vh8 v = ld16h<NT>(b + (size_t)site * 16);
+            const vh4 w = ld8h<NT>(b + (size_t)Vh * 16 + (size_t)site * 8);
 #pragma unroll
             for (int k = 0; k < 4; k++) e[k] = Cx<A>{(float)v[2 * k], (float)v[2 * k + 1]};
             e[4] = Cx<A>{(float)w[0], (float)w[1]};
@@ -1130,11 +1129,11 @@ struct LinkIO<HRD_SU3_ROW2, S> {
         for (int k = 0; k < 6; k++) e[k] = l.u[k / 3][k % 3];
         if constexpr (std::is_same<S, double>::value) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) st16d<false>(b + tile_off(Vh, site, k, 6), vd2{(double)e[k].re, (double)e[k].im});
+            for (int k = 0; k < 6; k++) st16d<false>(b + ((size_t)k * Vh + site) * 16, vd2{(double)e[k].re, (double)e[k].im});
         } else if constexpr (std::is_same<S, float>::value) {
 #pragma unroll
             for (int q = 0; q < 3; q++)
-                st16f<false>(b + tile_off(Vh, site, q, 3), vf4{(float)e[2 * q].re, (float)e[2 * q].im,
+                st16f<false>(b + ((size_t)q * Vh + site) * 16, vf4{(float)e[2 * q].re, (float)e[2 * q].im,
                                                                     (float)e[2 * q + 1].re, (float)e[2 * q + 1].im});
         } else {
             vh8 v;
@@ -1143,13 +1142,13 @@ struct LinkIO<HRD_SU3_ROW2, S> {
                 v[2 * k] = to_h16(e[k].re);
                 v[2 * k + 1] = to_h16(e[k].im);
             }
-            st16h<false>(b + tile_off(Vh, site, 0, 1, 8), v);
+            st16h<false>(b + (size_t)site * 16, v);
             vh4 w;
             w[0] = to_h16(e[4].re);
             w[1] = to_h16(e[4].im);
             w[2] = to_h16(e[5].re);
             w[3] = to_h16(e[5].im);
-            *reinterpret_cast<vh4 *>(b + tile_extra_off(Vh, site, 1, 8)) = w;
+            *reinterpret_cast<vh4 *>(b + (size_t)Vh * 16 + (size_t)site * 8) = w;
         }
     }
 };

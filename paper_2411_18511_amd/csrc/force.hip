@@ -49,8 +49,8 @@ __device__ __forceinline__ void force_dir(const Geom &g, const Site &s, int idx,
     };
     if constexpr (is_dense(REP)) {
         // dense formats, FP64 layout: entry e = N i + k in plane e (CPLXn:
-        // one complex per plane; REAL8: two reals per plane) of the site's
-        // 64-site tile, rows stored as they are formed
+        // one complex per plane; REAL8: two reals per plane), rows stored
+        // as they are formed
         char *blk = reinterpret_cast<char *>(F) +
                     (size_t)(4 * p + MU) * g.Vh * (size_t)link_bytes(REP, HRD_F64);
 #pragma unroll
@@ -59,13 +59,13 @@ __device__ __forceinline__ void force_dir(const Geom &g, const Site &s, int idx,
 #pragma unroll
                 for (int k = 0; k < N; k += 2) {
                     const int q = (N * i + k) / 2;
-                    st16d<false>(blk + tile_off(g.Vh, idx, q, N * N / 2), vd2{entry(i, k).re, entry(i, k + 1).re});
+                    st16d<false>(blk + ((size_t)q * g.Vh + idx) * 16, vd2{entry(i, k).re, entry(i, k + 1).re});
                 }
             } else {
 #pragma unroll
                 for (int k = 0; k < N; k++) {
                     const Cx<double> z = entry(i, k);
-                    st16d<false>(blk + tile_off(g.Vh, idx, N * i + k, N * N), vd2{z.re, z.im});
+                    st16d<false>(blk + ((size_t)(N * i + k) * g.Vh + idx) * 16, vd2{z.re, z.im});
                 }
             }
         }

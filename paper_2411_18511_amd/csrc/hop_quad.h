@@ -46,7 +46,7 @@ __device__ __forceinline__ void fence(Cx<double> (&v)[M])
 
 __device__ __forceinline__ Cx<double> sel_neg(bool neg, Cx<double> v) { return neg ? -v : v; }
 
-// A site in a 64-site tile of a REAL8 FP64 spinor or link block (32 planes): byte
+// A site in a 64-site tile of a REAL8 FP64 spinor block (32 planes): byte
 // offset of its plane 0 and the distance between its planes (32-bit; plane q
 // at base + q step, the offsets of tile_off).
 struct SiteOff {
@@ -87,19 +87,17 @@ __device__ __forceinline__ void project_k(const char *src, int Vh, int j, int k,
 }
 
 // u[i] = sum_b U[4hf + i][b] h[b] (rows streamed, row-wise FMA order of
-// dense_mul_rows); lb: the link block of (parity, direction), in 64-site
-// tiles of its 32 planes like a spinor block
+// dense_mul_rows); lb: the link block of (parity, direction)
 __device__ __forceinline__ void mul_rows(const char *lb, int Vh, int site, int hf, const Cx<double> (&h)[N],
                                          Cx<double> (&u)[4])
 {
-    const SiteOff so = site_off(Vh, site);
-    const uint32_t vo = so.base + (uint32_t)(4 * hf * kRowPlanes) * so.step;
+    const uint32_t vo = ((uint32_t)(4 * hf * kRowPlanes) * (uint32_t)Vh + (uint32_t)site) * 16u;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         double e[N];
 #pragma unroll
         for (int q = 0; q < kRowPlanes; q++) {
-            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (vo + (uint32_t)(i * kRowPlanes + q) * so.step));
+            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (size_t)(i * kRowPlanes + q) * Vh * 16 + vo);
             e[2 * q] = v.x;
             e[2 * q + 1] = v.y;
         }
@@ -115,14 +113,13 @@ __device__ __forceinline__ void mul_rows(const char *lb, int Vh, int site, int h
 __device__ __forceinline__ void mul_dag_rows(const char *lb, int Vh, int site, int hf, const Cx<double> (&h)[N],
                                              Cx<double> (&u)[4])
 {
-    const SiteOff so = site_off(Vh, site);
-    const uint32_t vo = so.base + (uint32_t)(2 * hf) * so.step;
+    const uint32_t vo = ((uint32_t)(2 * hf) * (uint32_t)Vh + (uint32_t)site) * 16u;
 #pragma unroll
     for (int J = 0; J < N; J++) {
         double e[4];
 #pragma unroll
         for (int q = 0; q < 2; q++) {
-            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (vo + (uint32_t)(J * kRowPlanes + q) * so.step));
+            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (size_t)(J * kRowPlanes + q) * Vh * 16 + vo);
             e[2 * q] = v.x;
             e[2 * q + 1] = v.y;
         }
