@@ -165,6 +165,30 @@ def test_mixed_cg_few_reliable_updates(oracle, mode, delta):
     assert res <= tol and info["iters"] > 24
 
 
+@pytest.mark.parametrize("mode", ["f64", "mixed", "mixed16"])
+def test_cg_on_side_stream(oracle, mode):
+    """The solver works on the caller's stream (torch's current stream), including
+    its pinned copies of the scalars and their events: the same solve on a second
+    stream (default priority) gives the same x, bit for bit, and the same
+    iteration count as on the default stream."""
+    h = hrd()
+    dims = (8, 4, 4, 8)
+    F = Field(dims, "fund", seed=71, kind="smeared")
+    U = {"f64": None, "mixed": F.U32, "mixed16": h.convert_gauge_prec(F.U64, dims, "fund", "f16")}[mode]
+    b = F.pack(oracle.restrict(F.spinor(72), 0), "f64", "even")
+    x0, i0 = h.cg_solve(F.U64, b, -0.3, 1e-10, dims, "fund", mode=mode, U32=U)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        x1, i1 = h.cg_solve(F.U64, b, -0.3, 1e-10, dims, "fund", mode=mode, U32=U)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert i1["iters"] == i0["iters"] and i1["reliable_updates"] == i0["reliable_updates"]
+    assert torch.equal(x0, x1)
+    assert oracle.true_residual(F.U_orc, oracle.restrict(F.spinor(72), 0), F.unpack(x1, "f64", "even"), -0.3) <= 1e-10
+
+
 def test_cg_errors(oracle):
     h = hrd()
     dims = (4, 4, 4, 4)
