@@ -195,6 +195,55 @@ def mixed_volume_cg(torch, hrd, inputs, dev, nrhs=12, tol=1e-10):
             "iters_batched_max": max(i["iters"] for i in infos), "iters_single_max": max(seq_iters)}
 
 
+def adjoint_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10, m0=-0.5):
+    """SU(2) with adjoint fermions on 32^4 (Haar links, m0 = -0.5): hopping block
+    and even/odd D^ in FP64 / FP32 / F16 for full (ADJ) and first-row (ADJ_SU2)
+    link storage, and CG to 1e-10 in every mode.  Timed once, outside the
+    per-step figures."""
+    V = int(np.prod(dims))
+    Uf = torch.from_numpy(inputs.gauge_field(dims, 11, kind="haar").reshape(4, V, 2, 2)).to(dev)
+    psi = torch.from_numpy(inputs.gaussian_spinor(dims, 3, 12).reshape(V, 4, 3)).to(dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    a, b = ev(), ev()
+    out = {"dims": list(dims), "m0": m0, "links": "Haar-random SU(2)"}
+    for fmt in ("adj", "adj_su2"):
+        U64 = hrd.represent(hrd.pack_gauge(Uf, dims, "fund", "f64"), dims, "f64") if fmt == "adj" else \
+            hrd.pack_gauge(Uf, dims, fmt, "f64")
+        src_o = hrd.pack_spinor(psi, dims, fmt, "f64", "odd")
+        src_e = hrd.pack_spinor(psi, dims, fmt, "f64", "even")
+        r = {}
+        lows = {}
+        for prec in ("f64", "f32", "f16"):
+            Ug = U64 if prec == "f64" else hrd.convert_gauge_prec(U64, dims, fmt, prec)
+            lows[prec] = Ug
+            so = hrd.convert_spinor_prec(src_o, dims, fmt, 1, "f64", prec)
+            se = hrd.convert_spinor_prec(src_e, dims, fmt, 1, "f64", prec)
+            dst = torch.empty_like(se)
+            L, S = LINK_BYTES[(fmt, prec)], SPINOR_BYTES[(fmt, prec)]
+            for kind, par, src, nrep, alg in (("hop", "hop_eo", so, reps, (V // 2) * (8 * L + 2 * S)),
+                                              ("dhat", "eo", se, reps // 2, V * 8 * L + (V // 2) * 5 * S)):
+                op = hrd.DiracOp(Ug, dims, fmt, prec, m0, par)
+                op(src, dst)
+                a.record()
+                for _ in range(nrep):
+                    op(src, dst)
+                b.record()
+                b.synchronize()
+                ms = a.elapsed_time(b) / nrep
+                r[f"{kind}_{prec}"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
+                                       "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del so, se, dst
+        for mode, Ulo in (("f64", None), ("mixed", lows["f32"]), ("mixed16", lows["f16"])):
+            a.record()
+            _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode=mode, U32=Ulo)
+            b.record()
+            b.synchronize()
+            r[f"cg_{mode}"] = {"ms": a.elapsed_time(b), **info}
+        out[fmt] = r
+        del U64, src_o, src_e, lows
+    return out
+
+
 SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx6": 36 * 16, "real8": 64 * 8, "su3_row2": 6 * 16}  # FP64, unpadded
 
 
@@ -575,6 +624,8 @@ def main():
     if batched_ok and not args.no_config4:
         out["batched_cg_mixed_volumes"] = mixed_volume_cg(torch, hrd, inputs, dev)
     if not args.no_sun:
+        print("[bench] SU(2) adjoint stage", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_stage(torch, hrd, inputs, dev)
         print("[bench] SU(3) representations stage", file=sys.stderr, flush=True)
         out["sun"] = sun_stage(torch, hrd, inputs, dev)
     if not args.no_cpu_baseline:
