@@ -86,3 +86,30 @@ def test_clover_queries(lib):
                                 None, None) == 1
     assert lib.hrd_clover_build(ctypes.byref(good), 0, 5, None, ctypes.c_double(1.0), ctypes.c_double(0.0), None,
                                 None, None) == 1
+
+
+@pytest.mark.parametrize("Vh", [1, 8, 63, 64, 65, 128, 360, 720, 1000])
+@pytest.mark.parametrize("P,extra", [(1, 0), (2, 0), (4, 0), (8, 0), (3, 4), (1, 2), (4, 8)])
+def test_tile_layout_is_a_bijection(Vh, P, extra):
+    """The 64-site tile layout documented in include/hrd.h places every
+    (plane, site) element and every trailing per-site entry exactly once inside
+    the block of Vh sites, without gaps: the block keeps the size of the plane
+    layout, Vh (16 P + extra) bytes, for any Vh (ragged last tile included)."""
+    import numpy as np
+
+    site = np.arange(Vh)
+    b0 = site & ~63
+    nb = np.minimum(64, Vh - b0)
+    tile = b0 * (16 * P + extra)
+    used = np.zeros(Vh * (16 * P + extra), dtype=np.int64)
+    for q in range(P):
+        off = tile + (q * nb + site - b0) * 16
+        assert (off % 16 == 0).all()
+        for k in range(16):
+            np.add.at(used, off + k, 1)
+    if extra:
+        off = tile + P * nb * 16 + (site - b0) * extra
+        assert (off % extra == 0).all()
+        for k in range(extra):
+            np.add.at(used, off + k, 1)
+    assert (used == 1).all()
