@@ -205,6 +205,11 @@ typedef struct {
 const char *hrd_last_error(void);
 /* Library version string. */
 const char *hrd_version(void);
+/* Hash of the sources the library was built from (16 hex digits: the first
+   64 bits of SHA-256 over the file names and contents of csrc/ and this
+   header, in name order), so a caller can refuse a stale build.  Static
+   string, never NULL. */
+const char *hrd_build_hash(void);
 
 /* ------------------------------------------------------------------------ */
 /* Sizes                                                                     */
@@ -583,6 +588,26 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
 hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, void *work,
                                 size_t work_bytes, const char *cache_path, hrd_tune *best,
                                 void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Bandwidth ceiling.  The operator is memory-bound (Sec. 2.1 and Table 1
+   state its performance as a fraction of the device's peak bandwidth); this
+   call streams a chosen read/write mix with the operator kernels' access
+   instructions (16-byte non-temporal loads and stores, the same block order)
+   so that the rate the device actually reaches for that mix can be measured
+   beside the kernels.                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* dst (write_bytes, a positive multiple of 16) receives, per 16-byte element,
+   the sum (as two float64) of k = read_bytes / write_bytes source elements
+   (1 <= k <= 64, read_bytes an exact multiple of write_bytes).  tiled = 0:
+   the source is k consecutive streams of write_bytes each (one array per
+   plane); tiled = 1: 64-element tiles, each wave reading one contiguous
+   stretch of 64 k elements (write_bytes a multiple of 1024).  src and dst
+   are caller-owned device buffers that must not overlap (HRD_EALIAS);
+   HRD_EINVAL for sizes outside these rules.  Asynchronous. */
+hrd_status hrd_stream_probe(const void *src, size_t read_bytes, void *dst, size_t write_bytes,
+                            int tiled, void *stream);
 
 #ifdef __cplusplus
 }

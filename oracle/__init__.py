@@ -58,6 +58,11 @@ def _load():
         lib.oracle_plaquette.argtypes = [P, ctypes.c_int, P]
         lib.oracle_plaquette.restype = ctypes.c_double
         lib.oracle_clover.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P]
+        lib.oracle_cg.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
+        lib.oracle_cg.restype = ctypes.c_int
+        lib.oracle_true_residual.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double]
+        lib.oracle_true_residual.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -225,6 +230,34 @@ def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None, op=None):
         iters += 1
     res = norm(b_e - op(x)) / bnorm
     return x, {"iters": iters, "true_rel_residual": res, "seconds": time.perf_counter() - t0}
+
+
+def cg_native(U, b_e, m0, tol=1e-10, maxiter=10000):
+    """The iteration of cg() (x0 = 0, default operator) run entirely in the C
+    part, for lattices where the numpy version is too slow.  Returns (x, info)
+    like cg()."""
+    dims = _dims_of_spinor(b_e)
+    n = b_e.shape[-1]
+    b = _cplx(b_e)
+    x = np.empty_like(b)
+    res = ctypes.c_double(0.0)
+    t0 = time.perf_counter()
+    it = _load().oracle_cg(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), _ptr(b), _ptr(x), float(m0),
+                           float(tol), int(maxiter), ctypes.byref(res))
+    if it < 0:
+        raise MemoryError("oracle_cg: temporaries could not be allocated")
+    return x, {"iters": it, "true_rel_residual": res.value, "seconds": time.perf_counter() - t0}
+
+
+def true_residual_native(U, b_e, x_e, m0):
+    """true_residual() evaluated in the C part (same operator as cg_native)."""
+    dims = _dims_of_spinor(b_e)
+    n = b_e.shape[-1]
+    res = _load().oracle_true_residual(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), _ptr(_cplx(b_e)),
+                                       _ptr(_cplx(x_e)), float(m0))
+    if res < 0:
+        raise MemoryError("oracle_true_residual: temporaries could not be allocated")
+    return res
 
 
 def true_residual(U, b_e, x_e, m0):

@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 typedef double complex cplx;
@@ -425,4 +426,174 @@ void oracle_clover(const int *d, int n, const cplx *U, double csw, cplx *A)
                                 a[(a1 * n + i) * ns + (b1 * n + j)] += csw * 0.25 * I * sig[a1][b1] * F[i * n + j];
             }
     }
+}
+
+/*
+ * Conjugate gradients on A = D^+ D^ over the even sites (the same iteration
+ * as the Python oracle's cg(), written out in C so that it finishes on the
+ * largest lattices):  D^ = m - (1/m) D_eo D_oe with m = 4 + m0 and
+ * D_eo = -H_eo / 2 (Sec. 2.1, even/odd preconditioned operator); D^+ =
+ * g5 D^ g5 with g5 = g0 g1 g2 g3.  Plain Hestenes-Stiefel from x = 0: stop when
+ * the recursively updated ||r|| <= tol ||b||, then recompute b - A x and go on
+ * from it if that check fails.  Fields are full-lattice arrays [V][4][n]
+ * whose odd sites are ignored on input and zero on output.  Returns the
+ * iteration count; *res receives the final ||b - A x|| / ||b||.  Uses
+ * 7 temporary full-lattice fields from the heap; returns -1 if they cannot
+ * be allocated.
+ */
+static int site_parity(const int *d, long s)
+{
+    int x[4];
+    coords(d, s, x);
+    return (x[0] + x[1] + x[2] + x[3]) & 1;
+}
+
+/* psi <- g5 psi, g5 = g0 g1 g2 g3 formed from the basis above */
+static void apply_g5(long V, int n, const cplx *in, cplx *out)
+{
+    cplx G[4][4][4], t[4][4], g5[4][4];
+    for (int mu = 0; mu < 4; mu++) gamma_matrix(mu, G[mu]);
+    memcpy(g5, G[0], sizeof(g5));
+    for (int mu = 1; mu < 4; mu++) {
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) {
+                cplx z = 0;
+                for (int k = 0; k < 4; k++) z += g5[a][k] * G[mu][k][b];
+                t[a][b] = z;
+            }
+        memcpy(g5, t, sizeof(g5));
+    }
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx v[4][MAXN];
+        for (int a = 0; a < 4; a++)
+            for (int i = 0; i < n; i++) {
+                cplx z = 0;
+                for (int b = 0; b < 4; b++) z += g5[a][b] * in[(s * 4 + b) * n + i];
+                v[a][i] = z;
+            }
+        for (int a = 0; a < 4; a++)
+            for (int i = 0; i < n; i++) out[(s * 4 + a) * n + i] = v[a][i];
+    }
+}
+
+/* out = D^ in on even sites (zero on odd); tmp: one full-lattice field */
+static void dhat_even(const int *d, int n, const cplx *U, const cplx *in, cplx *out, cplx *tmp, double m0)
+{
+    const long V = volume(d);
+    const double m = 4.0 + m0;
+    oracle_hopping(d, n, U, in, tmp, 2);  /* H_oe in on odd sites: reads even sites of in only */
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < V * 4 * n; k++) tmp[k] *= -0.5; /* D_oe in */
+    oracle_hopping(d, n, U, tmp, out, 1); /* H_eo (D_oe in) on even sites */
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        const int even = site_parity(d, s) == 0;
+        for (long k = s * 4 * n; k < (s + 1) * 4 * n; k++)
+            out[k] = even ? m * in[k] - (-0.5 * out[k]) / m : 0;
+    }
+}
+
+/* out = D^+ D^ in; t1, t2, t3: full-lattice temporaries */
+static void normal_even(const int *d, int n, const cplx *U, const cplx *in, cplx *out, cplx *t1, cplx *t2,
+                        cplx *t3, double m0)
+{
+    const long V = volume(d);
+    dhat_even(d, n, U, in, t1, t2, m0);
+    apply_g5(V, n, t1, t3);
+    dhat_even(d, n, U, t3, t1, t2, m0);
+    apply_g5(V, n, t1, out);
+}
+
+static double re_inner(long N, const cplx *a, const cplx *b)
+{
+    double s = 0;
+#pragma omp parallel for schedule(static) reduction(+ : s)
+    for (long k = 0; k < N; k++) s += creal(conj(a[k]) * b[k]);
+    return s;
+}
+
+int oracle_cg(const int *d, int n, const cplx *U, const cplx *b_in, cplx *x, double m0, double tol, int maxiter,
+              double *res)
+{
+    const long V = volume(d);
+    const long N = V * 4 * n;
+    cplx *b = malloc(sizeof(cplx) * N), *r = malloc(sizeof(cplx) * N), *p = malloc(sizeof(cplx) * N);
+    cplx *Ap = malloc(sizeof(cplx) * N), *t1 = malloc(sizeof(cplx) * N), *t2 = malloc(sizeof(cplx) * N);
+    cplx *t3 = malloc(sizeof(cplx) * N);
+    int it = -1;
+    if (!b || !r || !p || !Ap || !t1 || !t2 || !t3) goto done;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        const int even = site_parity(d, s) == 0;
+        for (long k = s * 4 * n; k < (s + 1) * 4 * n; k++) {
+            b[k] = even ? b_in[k] : 0;
+            x[k] = 0;
+            r[k] = b[k];
+            p[k] = b[k];
+        }
+    }
+    const double bnorm = sqrt(re_inner(N, b, b));
+    double rr = re_inner(N, r, r);
+    it = 0;
+    while (it < maxiter) {
+        if (sqrt(rr) <= tol * bnorm) {
+            normal_even(d, n, U, x, Ap, t1, t2, t3, m0);
+#pragma omp parallel for schedule(static)
+            for (long k = 0; k < N; k++) t1[k] = b[k] - Ap[k];
+            const double rt = re_inner(N, t1, t1);
+            if (sqrt(rt) <= tol * bnorm) break;
+            memcpy(r, t1, sizeof(cplx) * N);
+            memcpy(p, t1, sizeof(cplx) * N);
+            rr = rt;
+        }
+        normal_even(d, n, U, p, Ap, t1, t2, t3, m0);
+        const double alpha = rr / re_inner(N, p, Ap);
+#pragma omp parallel for schedule(static)
+        for (long k = 0; k < N; k++) {
+            x[k] += alpha * p[k];
+            r[k] -= alpha * Ap[k];
+        }
+        const double rr_new = re_inner(N, r, r);
+        const double beta = rr_new / rr;
+#pragma omp parallel for schedule(static)
+        for (long k = 0; k < N; k++) p[k] = r[k] + beta * p[k];
+        rr = rr_new;
+        it++;
+    }
+    normal_even(d, n, U, x, Ap, t1, t2, t3, m0);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < N; k++) t1[k] = b[k] - Ap[k];
+    *res = sqrt(re_inner(N, t1, t1)) / bnorm;
+done:
+    free(b), free(r), free(p), free(Ap), free(t1), free(t2), free(t3);
+    return it;
+}
+
+/* ||b - D^+ D^ x|| / ||b|| over the even sites (odd sites of b and x are
+   ignored), with the operator of oracle_cg.  Returns -1 if the temporaries
+   cannot be allocated. */
+double oracle_true_residual(const int *d, int n, const cplx *U, const cplx *b_in, const cplx *x_in, double m0)
+{
+    const long V = volume(d);
+    const long N = V * 4 * n;
+    cplx *b = malloc(sizeof(cplx) * N), *x = malloc(sizeof(cplx) * N), *Ax = malloc(sizeof(cplx) * N);
+    cplx *t1 = malloc(sizeof(cplx) * N), *t2 = malloc(sizeof(cplx) * N), *t3 = malloc(sizeof(cplx) * N);
+    double res = -1;
+    if (b && x && Ax && t1 && t2 && t3) {
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < V; s++) {
+            const int even = site_parity(d, s) == 0;
+            for (long k = s * 4 * n; k < (s + 1) * 4 * n; k++) {
+                b[k] = even ? b_in[k] : 0;
+                x[k] = even ? x_in[k] : 0;
+            }
+        }
+        normal_even(d, n, U, x, Ax, t1, t2, t3, m0);
+#pragma omp parallel for schedule(static)
+        for (long k = 0; k < N; k++) t1[k] = b[k] - Ax[k];
+        res = sqrt(re_inner(N, t1, t1) / re_inner(N, b, b));
+    }
+    free(b), free(x), free(Ax), free(t1), free(t2), free(t3);
+    return res;
 }

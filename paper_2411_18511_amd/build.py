@@ -7,6 +7,7 @@ is off (the kernels fuse explicitly where they mean to).
 """
 import concurrent.futures
 import glob
+import hashlib
 import os
 import subprocess
 
@@ -34,9 +35,28 @@ CFLAGS = [
 ]
 
 
-def _compile(src, verbose, build_dir=BUILD):
+def source_files():
+    """Every file the library is built from, in name order."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))) + \
+        [os.path.join(INCLUDE, "hrd.h")]
+
+
+def source_hash() -> str:
+    """First 64 bits (hex) of SHA-256 over the names and contents of the
+    library's sources; compiled into the library (hrd_build_hash) and checked
+    by the binding at import."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.relpath(f, ROOT).encode())
+        h.update(b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, verbose, build_dir=BUILD, src_hash=None):
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = ["hipcc", "-c", src, "-o", obj] + CFLAGS
+    cmd = ["hipcc", "-c", src, "-o", obj] + CFLAGS + [f'-DHRD_SOURCE_HASH="{src_hash or source_hash()}"']
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,8 +70,9 @@ def _compile(src, verbose, build_dir=BUILD):
 def build(verbose: bool = False, jobs: int = 8, lib_path: str = LIB, build_dir: str = BUILD) -> str:
     os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    h = source_hash()
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, h), srcs))
     tmp = lib_path + ".tmp"
     cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

@@ -298,7 +298,13 @@ extern "C" {
 
 const char *hrd_last_error(void) { return g_last_error.c_str(); }
 
-const char *hrd_version(void) { return "hrd 0.1 (gfx950)"; }
+#ifndef HRD_SOURCE_HASH
+#error "HRD_SOURCE_HASH must be defined by the build (hash of the library sources)"
+#endif
+
+const char *hrd_version(void) { return "hrd 0.2 (gfx950, sources " HRD_SOURCE_HASH ")"; }
+
+const char *hrd_build_hash(void) { return HRD_SOURCE_HASH; }
 
 size_t hrd_spinor_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, int nparity)
 {
@@ -488,6 +494,16 @@ size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec p
 hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *psi,
                            void *out, double m0, hrd_parity parity, int dagger, void *work, void *stream)
 {
+    return hrd::dirac_apply_checked(lat, rep, prec, U, psi, out, m0, parity, dagger, work, stream);
+}
+
+}  // extern "C"
+
+namespace hrd {
+
+hrd_status dirac_apply_checked(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *psi,
+                               void *out, double m0, hrd_parity parity, int dagger, void *work, void *stream)
+{
     HRD_TRY(check_lattice(lat));
     HRD_TRY(check_rep_prec_any(rep, prec));
     if (parity < HRD_FULL || parity > HRD_HOP_OE) return fail(HRD_EINVAL, "invalid parity mode %d", (int)parity);
@@ -515,6 +531,10 @@ hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, c
     }
     return check_hip(e, "dirac_apply launch");
 }
+
+}  // namespace hrd
+
+extern "C" {
 
 size_t hrd_clover_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec)
 {

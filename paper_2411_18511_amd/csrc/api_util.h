@@ -49,4 +49,9 @@ hipError_t apply_hop_block(int rep, int prec, const Geom &g, const void *U, cons
 hipError_t apply_full(int rep, int prec, const Geom &g, const void *U, const void *in, void *out, double m0,
                       bool dag, hipStream_t st, const CloverRef *cl = nullptr);
 
+// hrd_dirac_apply after its argument checks (work: the caller's HRD_EO
+// workspace, checked for overlaps like any caller buffer).
+hrd_status dirac_apply_checked(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec, const void *U, const void *psi,
+                               void *out, double m0, hrd_parity parity, int dagger, void *work, void *stream);
+
 }  // namespace hrd

@@ -24,6 +24,20 @@ if not os.path.exists(LIBPATH):
     raise ImportError(f"libhrd.so not found at {LIBPATH}; build it with __graft_entry__.build()")
 
 _lib = ctypes.CDLL(LIBPATH)
+_lib.hrd_build_hash.restype = ctypes.c_char_p
+
+
+def _check_build():
+    from . import build as _build
+
+    want = _build.source_hash()
+    have = _lib.hrd_build_hash().decode()
+    if have != want:
+        raise ImportError(f"libhrd.so was built from other sources (library {have}, tree {want}); "
+                          "rebuild it with __graft_entry__.build()")
+
+
+_check_build()
 
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
@@ -137,6 +151,7 @@ _sig("hrd_cg_solve_clover", _I, _LP, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _D,
 _sig("hrd_dirac_force", _I, _LP, _I, _I, _P, _P, _P, _P, _D, _P)
 _sig("hrd_action_force_workspace_bytes", _S, _LP, _I)
 _sig("hrd_action_force", _I, _LP, _I, _P, _P, _P, _D, _D, _P, _S, _P)
+_sig("hrd_stream_probe", _I, _P, _S, _P, _S, _I, _P)
 _HAS_BATCHED = hasattr(_lib, "hrd_dirac_apply_batched")
 if _HAS_BATCHED:
     _sig("hrd_batched_workspace_bytes", _S, ctypes.POINTER(Problem), _I, _I)
@@ -156,6 +171,11 @@ def _check(status, allow=()):
 
 def version():
     return _lib.hrd_version().decode()
+
+
+def build_hash():
+    """Hash of the sources the loaded library was built from (equal to the tree's)."""
+    return _lib.hrd_build_hash().decode()
 
 
 def lattice(dims):
@@ -689,3 +709,17 @@ def autotune_batched(problems, cache_path=None, work=None, device="cuda"):
     _check(_lib.hrd_autotune_batched(problems, len(problems), _ptr(work), wb,
                                      cache_path.encode() if cache_path else None, ctypes.byref(best), _stream()))
     return best.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# bandwidth ceiling
+# ---------------------------------------------------------------------------
+
+def stream_probe(src, dst, read_bytes, write_bytes, tiled=True):
+    """Stream read_bytes of src and write write_bytes of dst (k = read/write
+    16-byte loads per store) with the operator kernels' access instructions;
+    asynchronous on torch's current stream."""
+    _need(src, read_bytes, "stream_probe src")
+    _need(dst, write_bytes, "stream_probe dst")
+    _check(_lib.hrd_stream_probe(_ptr(src), int(read_bytes), _ptr(dst), int(write_bytes), int(bool(tiled)),
+                                 _stream()))

@@ -113,3 +113,14 @@ def test_tile_layout_is_a_bijection(Vh, P, extra):
         for k in range(extra):
             np.add.at(used, off + k, 1)
     assert (used == 1).all()
+
+
+def test_library_was_built_from_this_tree(lib):
+    """The build compiles the hash of the library sources into libhrd.so, and
+    the binding refuses a library whose hash differs from the tree's."""
+    from paper_2411_18511_amd import build
+
+    lib.hrd_build_hash.restype = ctypes.c_char_p
+    assert lib.hrd_build_hash().decode() == build.source_hash()
+    lib.hrd_version.restype = ctypes.c_char_p
+    assert build.source_hash().encode() in lib.hrd_version()

@@ -256,3 +256,32 @@ def test_cg_matches_dense_solve(oracle, n):
     e, _ = dense.parity_index(dims, n)
     xd = np.linalg.solve(S.conj().T @ S, b.ravel()[e])
     assert np.linalg.norm(x.ravel()[e] - xd) / np.linalg.norm(xd) < 1e-8
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_native_cg_matches_dense_solve(oracle, n):
+    """The C iteration of the oracle CG (used on the large lattices) solves the
+    dense even/odd system, takes the same iterations as the numpy one, and its
+    true residual routine equals the numpy one on an arbitrary x."""
+    dims = (4, 4, 4, 4) if n == 2 else (4, 4, 2, 4)
+    m0 = -0.2
+    U = _links(dims, n, 93, oracle)
+    b = oracle.restrict(_field(dims, n, 94), 0)
+    x, info = oracle.cg_native(U, b, m0, tol=1e-11)
+    _, info_py = oracle.cg(U, b, m0, tol=1e-11)
+    assert info["iters"] == info_py["iters"]
+    assert info["true_rel_residual"] <= 1e-11
+    assert np.all(x[oracle.parity(dims) == 1] == 0)
+    D = dense.dirac_matrix(U, m0)
+    Dee, Deo, Doe, Doo = dense.schur_blocks(D, dims, n)
+    S = Dee - Deo @ Doe / (4 + m0)
+    e, _ = dense.parity_index(dims, n)
+    xd = np.linalg.solve(S.conj().T @ S, b.ravel()[e])
+    assert np.linalg.norm(x.ravel()[e] - xd) / np.linalg.norm(xd) < 1e-9
+    y = _field(dims, n, 95)
+    r_py = oracle.true_residual(U, b, y, m0)
+    assert abs(oracle.true_residual_native(U, b, y, m0) - r_py) < 1e-13 * r_py
+    # a dropped term in the operator would move the residual of the dense solution
+    xs = np.zeros_like(b)
+    xs.reshape(-1)[e] = xd
+    assert oracle.true_residual_native(U, b, xs, m0) < 1e-11
