@@ -108,7 +108,10 @@
  * OWNERSHIP AND ERRORS
  *   Every field pointer is a device pointer owned by the caller; the library
  *   never allocates device memory: temporaries come from caller-provided
- *   workspaces whose sizes the *_bytes queries return.  Calls are enqueued on
+ *   workspaces whose sizes the *_bytes queries return.
+ *   The CG solvers read their scalars through a small pinned host buffer and
+ *   two events, created on a host thread's first solve on a device and kept
+ *   until the process ends.  Calls are enqueued on
  *   the given stream (a hipStream_t; NULL means the null stream) and return
  *   without synchronising unless stated.  No call aborts or throws: each
  *   returns an hrd_status, and hrd_last_error() gives a thread-local message
@@ -539,9 +542,14 @@ typedef struct {
 
 /* Launch shape of the batched kernels: sites per tile (64, 128 or 256; one
    thread per site, so also the threads per workgroup), right-hand sides
-   processed per tile (1, 2, 3, 4 or 6), workgroups per CU of the persistent
-   grid, and the x1-slab width of the traversal (rounded down to a divisor of
-   each problem's L1).  Zero fields select defaults. */
+   processed per tile (1..64), workgroups per CU of the persistent grid
+   (1..16), and the x1-slab width of the traversal (rounded down to a divisor
+   of each problem's L1; larger than L1 means lexicographic order).  Zero
+   fields select the defaults (128 sites, 4 right-hand sides, 4 workgroups per
+   CU, automatic slab); other values outside these ranges give HRD_EINVAL.
+   block_threads is ignored (always sites_per_tile).  hrd_autotune_batched
+   tries sites {64, 128, 256} x right-hand sides {1, 2, 4, 6, 12} x
+   workgroups per CU {2, 4, 8} x slabs {automatic, 1, 2, 4, 8, L1}. */
 typedef struct {
     int sites_per_tile;
     int rhs_per_tile;

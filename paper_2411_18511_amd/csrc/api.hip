@@ -213,7 +213,16 @@ hrd_status read_scalars(const double *sc_dev, double *host, hipStream_t st)
 
 // Two pinned host copies of the CG scalars, each with an event, so that the
 // host reads iteration k's scalars while the stream already runs the first
-// stage of iteration k + 1.
+// stage of iteration k + 1.  The pinned buffer and the events are created on a
+// host thread's first solve on a device and kept for the life of the process
+// (one set per host thread and device), so a solve allocates nothing and
+// never pays hipHostFree's implicit synchronisation.
+struct PinnedScalars {
+    double *h = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+constexpr int kMaxScalarDevices = 64;
+
 struct ScalarPipe {
     hipStream_t st;
     double *h = nullptr;
@@ -223,10 +232,22 @@ struct ScalarPipe {
     ScalarPipe &operator=(const ScalarPipe &) = delete;
     hrd_status init()
     {
-        hipError_t e = hipHostMalloc((void **)&h, sizeof(double) * 2 * S_COUNT, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
-        return check_hip(e, "pinned CG scalars");
+        static thread_local PinnedScalars pool[kMaxScalarDevices];
+        int dev = -1;
+        HRD_TRY(check_hip(hipGetDevice(&dev), "hipGetDevice"));
+        if (dev < 0 || dev >= kMaxScalarDevices) return fail(HRD_EINVAL, "device ordinal %d out of range", dev);
+        PinnedScalars &ps = pool[dev];
+        if (!ps.ev[1]) {
+            hipError_t e = hipSuccess;
+            if (!ps.h) e = hipHostMalloc((void **)&ps.h, sizeof(double) * 2 * S_COUNT, hipHostMallocDefault);
+            if (e == hipSuccess && !ps.ev[0]) e = hipEventCreateWithFlags(&ps.ev[0], hipEventDisableTiming);
+            if (e == hipSuccess && !ps.ev[1]) e = hipEventCreateWithFlags(&ps.ev[1], hipEventDisableTiming);
+            HRD_TRY(check_hip(e, "pinned CG scalars"));
+        }
+        h = ps.h;
+        ev[0] = ps.ev[0];
+        ev[1] = ps.ev[1];
+        return HRD_OK;
     }
     hrd_status post(const double *sc_dev, int slot)
     {
@@ -244,10 +265,8 @@ struct ScalarPipe {
     }
     ~ScalarPipe()
     {
-        if (h) (void)hipStreamSynchronize(st);  // no copy into h may still be in flight
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-        if (h) (void)hipHostFree(h);
+        // the next solve on this thread reuses h: no copy into it may still be in flight
+        if (h) (void)hipStreamSynchronize(st);
     }
 };
 
@@ -753,7 +772,6 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     const hipStream_t st = (hipStream_t)stream;
     const int nc = ncomp_of(rep);
     const size_t n64 = h64 / 16;
-    const size_t n32 = spinor_bytes(lat, rep, HRD_F32, 1) / 16;
     const int hb = hop_blocks(g);
     double sc[S_COUNT];
 

@@ -25,13 +25,6 @@
 #include "api_util.h"
 #include "spin.h"
 
-// 1: each thread holds its site's 8 links in registers across the group of
-// right-hand sides; 0: the links are re-read (from L2 after the first) for
-// each right-hand side, which leaves the registers for more loads in flight.
-#ifndef HRD_BLINKS_REGS
-#define HRD_BLINKS_REGS 1
-#endif
-
 namespace hrd {
 
 namespace {
@@ -136,10 +129,8 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
         for (int mu = 0; mu < 4; mu++) {
             jf[mu] = nbr_fwd(g, s, mu);
             jb[mu] = nbr_bwd(g, s, mu);
-            if constexpr (HRD_BLINKS_REGS) {
-                lf[mu] = LIO::template load<true>(d.U32, g.Vh, parity, mu, idx);
-                lb[mu] = LIO::template load<true>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
-            }
+            lf[mu] = LIO::template load<true>(d.U32, g.Vh, parity, mu, idx);
+            lb[mu] = LIO::template load<true>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
         }
         nf = s.x[0] == g.L[0] - 1;
         nb = s.x[0] == 0;
@@ -151,13 +142,6 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
         if (mode && mode[d.rhs_base + rhs] == M_DONE) continue;  // uniform
         double nrm = 0;
         if (in) {
-            if constexpr (!HRD_BLINKS_REGS) {
-#pragma unroll
-                for (int mu = 0; mu < 4; mu++) {
-                    lf[mu] = LIO::template load<false>(d.U32, g.Vh, parity, mu, idx);
-                    lb[mu] = LIO::template load<false>(d.U32, g.Vh, 1 - parity, mu, jb[mu]);
-                }
-            }
             const char *src = d.buf[src_id] + (size_t)rhs * d.fbytes;
             Cx<float> acc[NC];
 #pragma unroll
@@ -931,9 +915,17 @@ extern "C" hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, 
     const std::string key = tune_key(probs, nprob);
     if (cache_path && cache_lookup(cache_path, key, best)) return HRD_OK;
     const hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    HRD_TRY(check_hip(hipEventCreate(&e0), "event"));
-    HRD_TRY(check_hip(hipEventCreate(&e1), "event"));
+    // the two timing events, destroyed on every return path
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    HRD_TRY(check_hip(hipEventCreate(&ev.e[0]), "hipEventCreate"));
+    HRD_TRY(check_hip(hipEventCreate(&ev.e[1]), "hipEventCreate"));
     const int sites[] = {64, 128, 256};
     const int groups[] = {1, 2, 4, 6, 12};
     const int bpc[] = {2, 4, 8};
@@ -943,32 +935,27 @@ extern "C" hrd_status hrd_autotune_batched(const hrd_problem *probs, int nprob, 
     for (int s : sites)
         for (int gsz : groups)
             for (int b : bpc)
-              for (int sl : slabs) {
-                const hrd_tune cand{s, gsz, s, b, sl};
-                hrd_status rc = hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream);
-                if (rc != HRD_OK) {
-                    (void)hipEventDestroy(e0);
-                    (void)hipEventDestroy(e1);
-                    return rc;
+                for (int sl : slabs) {
+                    const hrd_tune cand{s, gsz, s, b, sl};
+                    // one untimed launch, then the median of 5 timed ones; any
+                    // failed launch or event call ends the search with its status
+                    HRD_TRY(hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream));
+                    float times[5];
+                    for (int rep = 0; rep < 5; rep++) {
+                        HRD_TRY(check_hip(hipEventRecord(ev.e[0], st), "hipEventRecord"));
+                        HRD_TRY(hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream));
+                        HRD_TRY(check_hip(hipEventRecord(ev.e[1], st), "hipEventRecord"));
+                        HRD_TRY(check_hip(hipEventSynchronize(ev.e[1]), "hipEventSynchronize"));
+                        HRD_TRY(check_hip(hipEventElapsedTime(&times[rep], ev.e[0], ev.e[1]), "hipEventElapsedTime"));
+                    }
+                    std::sort(times, times + 5);
+                    const float med = times[2];
+                    // ties (within 1%) go to the earlier, smaller candidate
+                    if (med < best_ms * 0.99f) {
+                        best_ms = med;
+                        bt = cand;
+                    }
                 }
-                float times[5];
-                for (int rep = 0; rep < 5; rep++) {
-                    (void)hipEventRecord(e0, st);
-                    hrd_dirac_apply_batched(probs, nprob, HRD_EO, 0, &cand, work, work_bytes, stream);
-                    (void)hipEventRecord(e1, st);
-                    (void)hipEventSynchronize(e1);
-                    (void)hipEventElapsedTime(&times[rep], e0, e1);
-                }
-                std::sort(times, times + 5);
-                const float med = times[2];
-                // ties (within 1%) go to the smaller tile
-                if (med < best_ms * 0.99f) {
-                    best_ms = med;
-                    bt = cand;
-                }
-            }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     *best = bt;
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");

@@ -10,7 +10,6 @@ namespace hrd {
 // source slice is then 0.9 MB and the t-1, t, t+1 slices stay in a 4 MB L2).
 int choose_slab(const int dims[4])
 {
-    if (HRD_SLAB > 0 && dims[1] % HRD_SLAB == 0) return HRD_SLAB;
     constexpr long kSlabSites = 6912;
     const long R = (long)dims[2] * dims[3] / 2;
     int best = 1;
@@ -25,7 +24,6 @@ int choose_slab(const int dims[4])
 // 821 -> 742 us with slab 3 instead of 6; FP32 best at the default slab).
 int choose_slab_full(const int dims[4], int prec)
 {
-    if (HRD_SLAB > 0 && dims[1] % HRD_SLAB == 0) return HRD_SLAB;
     const long budget = prec == HRD_F64 ? 3456 : 6912;
     const long R = (long)dims[2] * dims[3] / 2;
     int best = 1;

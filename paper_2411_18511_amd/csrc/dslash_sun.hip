@@ -4,10 +4,6 @@
 #include "hop_quad.h"
 
 // REAL8 links in FP64 run on the four-lanes-per-site kernel of hop_quad.h
-#ifndef HRD_QUAD_REAL8
-#define HRD_QUAD_REAL8 1
-#endif
-
 namespace hrd {
 
 namespace {
@@ -16,7 +12,7 @@ template <typename S>
 hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st,
                          int clov)
 {
-    if constexpr (HRD_QUAD_REAL8 && std::is_same<S, double>::value)
+    if constexpr (std::is_same<S, double>::value)
         if (quad_covers(rep, full, a.g.Vh)) return launch_hop_quad(a, dag, has_a, norm, st);
     switch (rep) {
         case HRD_CPLX3: return dispatch_hop_clov<HRD_CPLX3, S>(a, dag, has_a, norm, full, st, clov);
@@ -30,7 +26,7 @@ hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool n
 template <typename S>
 hipError_t dense_rupd_for(int rep, const HopArgs &a, hipStream_t st, int clov)
 {
-    if constexpr (HRD_QUAD_REAL8 && std::is_same<S, double>::value)
+    if constexpr (std::is_same<S, double>::value)
         if (quad_covers(rep, false, a.g.Vh)) return launch_hop_quad_rupdate(a, st);
     switch (rep) {
         case HRD_CPLX3: return dispatch_rupd<HRD_CPLX3, S>(a, st, clov);

@@ -20,41 +20,19 @@
 #include "kernels.h"
 #include "spin.h"
 
-// Launch-shape and cache-policy choices of the hopping kernel (measured on
-// MI355X; see the design notes): non-temporal link loads and output stores,
-// minimum waves per SIMD, and the x1-slab width of the traversal (0: chosen
-// per lattice by choose_slab).
-// Non-temporal link loads in the FULL (both parities in one launch) kernel:
-// there every link is used by one even and one odd target, and the blocks of
-// the two parities at the same position run side by side on one XCD.
-#ifndef HRD_NT_LINKS_FULL
-#define HRD_NT_LINKS_FULL 0
-#endif
-#ifndef HRD_NT_LINKS
-#define HRD_NT_LINKS 1
-#endif
-#ifndef HRD_NT_STORE
-#define HRD_NT_STORE 1
-#endif
-#ifndef HRD_HOP_WAVES
-#define HRD_HOP_WAVES 1
-#endif
-#ifndef HRD_SLAB
-#define HRD_SLAB 0
-#endif
-#ifndef HRD_HOP_BLOCK
-#define HRD_HOP_BLOCK 256
-#endif
-// SU(2) formats: 0 lets the compiler overlap all eight direction terms; 1
-// fences after each direction (forward and backward term), 2 after each term,
-// 3 after every second direction.
-#ifndef HRD_FENCE
-#define HRD_FENCE 0
-#endif
-
 namespace hrd {
 
-constexpr int kHopBlock = HRD_HOP_BLOCK;  // threads per workgroup of the hopping kernel
+// Launch shape and cache policy of the hopping kernel (measured on MI355X):
+// 256-thread workgroups; links and outputs are used once per hop and go
+// through non-temporal loads and stores, except in the one-launch plain
+// operator, where every link serves one even and one odd target and the
+// blocks of the two parities at the same position run side by side on one
+// XCD (temporal link loads).
+constexpr bool kNtLinks = true;
+constexpr bool kNtLinksFull = false;
+constexpr bool kNtStore = true;
+
+constexpr int kHopBlock = 256;  // threads per workgroup of the hopping kernel
 
 namespace {
 
@@ -72,7 +50,7 @@ __device__ __forceinline__ void dir_fence(Cx<R> (&acc)[NC])
 }
 
 // S: storage type of the source spinor and the links; R: arithmetic type.
-template <int MU, bool DAG, int REP, typename S, bool NTL = HRD_NT_LINKS, typename R = typename Arith<S>::type>
+template <int MU, bool DAG, int REP, typename S, bool NTL = kNtLinks, typename R = typename Arith<S>::type>
 __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, int p, const void *U,
                                         const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
 {
@@ -100,7 +78,6 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
         link_mul(l, h1, u1);
         reconstruct<MU, SF, N, R>(acc, u0, u1);
     }
-    if constexpr (HRD_FENCE == 2) dir_fence(acc);
     {
         const int j = nbr_bwd(g, s, MU);
         Cx<R> psi[NC];
@@ -126,7 +103,7 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
 template <int REP, typename S, int I, typename T, int N>
 __device__ __forceinline__ void dense_row(const void *U, int Vh, int p, int mu, int site, T (&row)[N])
 {
-    LinkIO<REP, S>::template load_row<I, HRD_NT_LINKS>(U, Vh, p, mu, site, row);
+    LinkIO<REP, S>::template load_row<I, kNtLinks>(U, Vh, p, mu, site, row);
 }
 
 template <typename R>
@@ -238,7 +215,7 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
             }
         }
         if constexpr (dense_whole_link<REP, S>()) {
-            const auto l = LinkIO<REP, S>::template load<HRD_NT_LINKS>(U, g.Vh, p, MU, idx);
+            const auto l = LinkIO<REP, S>::template load<kNtLinks>(U, g.Vh, p, MU, idx);
             link_mul(l, h0, u0);
             link_mul(l, h1, u1);
         } else {
@@ -263,7 +240,7 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
             }
         }
         if constexpr (dense_whole_link<REP, S>()) {
-            const auto l = LinkIO<REP, S>::template load<HRD_NT_LINKS>(U, g.Vh, 1 - p, MU, j);
+            const auto l = LinkIO<REP, S>::template load<kNtLinks>(U, g.Vh, 1 - p, MU, j);
             link_mul_dag(l, h0, u0);
             link_mul_dag(l, h1, u1);
         } else {
@@ -281,7 +258,7 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
 // h16), R = Arith<S>::type the arithmetic; the residual of the RUPD epilogue
 // and the clover fields are stored in R.
 template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE>
-__global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
 {
     using R = typename Arith<S>::type;
     constexpr int N = NCol<REP>::value;
@@ -319,13 +296,10 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             hop_dir_dense<2, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
             hop_dir_dense<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         } else {
-            constexpr bool NTL = FULL ? HRD_NT_LINKS_FULL : HRD_NT_LINKS;
+            constexpr bool NTL = FULL ? kNtLinksFull : kNtLinks;
             hop_dir<0, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
             hop_dir<1, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            if constexpr (HRD_FENCE >= 1) dir_fence(acc);
             hop_dir<2, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            if constexpr (HRD_FENCE == 1 || HRD_FENCE == 2) dir_fence(acc);
             hop_dir<3, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
         }
         const R cb = (R)a.b;
@@ -334,11 +308,11 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
             Cx<R> t[NC];
 #pragma unroll
             for (int k = 0; k < NC; k++) t[k] = cb * acc[k];
-            clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, t, out);
+            clover_apply<N, R, kNtLinks>(a.clov, g.Vh, p, idx, t, out);
         } else if constexpr (HAS_A && CLOV == CLOV_SELF) {
             Cx<R> self_v[NC], ms[NC];
             SpinorIO<S>::template load<NC>(self, g.Vh, idx, self_v);
-            clover_apply<N, R, HRD_NT_LINKS>(a.clov, g.Vh, p, idx, self_v, ms);
+            clover_apply<N, R, kNtLinks>(a.clov, g.Vh, p, idx, self_v, ms);
 #pragma unroll
             for (int k = 0; k < NC; k++)
                 out[k] = Cx<R>{fmadd(cb, acc[k].re, ms[k].re), fmadd(cb, acc[k].im, ms[k].im)};
@@ -362,9 +336,9 @@ __global__ __launch_bounds__(kHopBlock, HRD_HOP_WAVES) void hop_kernel(HopArgs a
                 rv[k] = Cx<R>{fmadd(-alpha, out[k].re, rv[k].re), fmadd(-alpha, out[k].im, rv[k].im)};
                 nrm += (double)rv[k].re * (double)rv[k].re + (double)rv[k].im * (double)rv[k].im;
             }
-            SpinorIO<R>::template store<NC, HRD_NT_STORE>(a.r, g.Vh, idx, rv);
+            SpinorIO<R>::template store<NC, kNtStore>(a.r, g.Vh, idx, rv);
         } else {
-            SpinorIO<S>::template store<NC, HRD_NT_STORE>(dst, g.Vh, idx, out);
+            SpinorIO<S>::template store<NC, kNtStore>(dst, g.Vh, idx, out);
             if constexpr (NORM) {
 #pragma unroll
                 for (int k = 0; k < NC; k++)

@@ -97,7 +97,7 @@ __device__ __forceinline__ void mul_rows(const char *lb, int Vh, int site, int h
         double e[N];
 #pragma unroll
         for (int q = 0; q < kRowPlanes; q++) {
-            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (size_t)(i * kRowPlanes + q) * Vh * 16 + vo);
+            const vd2 v = ld16d<kNtLinks>(lb + (size_t)(i * kRowPlanes + q) * Vh * 16 + vo);
             e[2 * q] = v.x;
             e[2 * q + 1] = v.y;
         }
@@ -119,7 +119,7 @@ __device__ __forceinline__ void mul_dag_rows(const char *lb, int Vh, int site, i
         double e[4];
 #pragma unroll
         for (int q = 0; q < 2; q++) {
-            const vd2 v = ld16d<HRD_NT_LINKS>(lb + (size_t)(J * kRowPlanes + q) * Vh * 16 + vo);
+            const vd2 v = ld16d<kNtLinks>(lb + (size_t)(J * kRowPlanes + q) * Vh * 16 + vo);
             e[2 * q] = v.x;
             e[2 * q + 1] = v.y;
         }
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kQuadBlock) void hop_quad_kernel(HopArgs a)
         }
 #pragma unroll
         for (int i = 0; i < 8; i++) {
-            st16d<HRD_NT_STORE>(dst + ((i < 4 ? vu : vl) + (uint32_t)(i & 3) * si.step), vd2{out[i].re, out[i].im});
+            st16d<kNtStore>(dst + ((i < 4 ? vu : vl) + (uint32_t)(i & 3) * si.step), vd2{out[i].re, out[i].im});
             if constexpr (NORM || RUPD) nrm += out[i].re * out[i].re + out[i].im * out[i].im;
         }
     }

@@ -55,6 +55,19 @@ def rel_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def site_rel_err(a, b):
+    """Largest per-site relative error max_x ||a(x) - b(x)|| / ||b(x)|| over the
+    sites where b(x) is nonzero (fields [T, L1, L2, L3, 4, N] or [..., N, N]);
+    sites where b(x) = 0 must have a(x) = 0 exactly."""
+    a = np.asarray(a).reshape(int(np.prod(a.shape[:4])), -1)
+    b = np.asarray(b).reshape(a.shape)
+    nb = np.linalg.norm(b, axis=1)
+    nd = np.linalg.norm(a - b, axis=1)
+    zero = nb == 0
+    assert np.all(nd[zero] == 0), "output nonzero where the reference is zero"
+    return float((nd[~zero] / nb[~zero]).max()) if (~zero).any() else 0.0
+
+
 class Field:
     """A seeded problem: fundamental links, optional adjoint links, packed on the GPU."""
 
