@@ -108,7 +108,8 @@
  * OWNERSHIP AND ERRORS
  *   Every field pointer is a device pointer owned by the caller; the library
  *   never allocates device memory: temporaries come from caller-provided
- *   workspaces whose sizes the *_bytes queries return.
+ *   workspaces whose sizes the *_bytes queries return (the one exception,
+ *   hrd_dirac_apply_static, keeps its temporary in a static device array).
  *   The CG solvers read their scalars through a small pinned host buffer and
  *   two events, created on a host thread's first solve on a device and kept
  *   until the process ends.  Calls are enqueued on
@@ -338,6 +339,23 @@ size_t hrd_dirac_workspace_bytes(const hrd_lattice *lat, hrd_rep rep, hrd_prec p
 hrd_status hrd_dirac_apply(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
                            const void *U, const void *psi, void *out, double m0,
                            hrd_parity parity, int dagger, void *work, void *stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): hrd_dirac_apply without
+   a workspace argument.  HRD_EO keeps its odd temporary in a static device
+   array of hrd_dirac_static_scratch_bytes() bytes (64 MiB) that each device
+   the library runs on holds until the process ends; an HRD_EO call whose
+   temporary (hrd_dirac_workspace_bytes) exceeds it returns HRD_ESIZE.  The
+   other parity modes use no temporary.  The array is shared by every call on
+   a device, so calls that overlap on one device (different streams not
+   ordered by the caller) race; it holds the last call's temporary, which
+   every call rewrites before reading.  Never allocates or frees memory; the
+   first call on a device looks up the array's device address.  Results equal
+   hrd_dirac_apply's bit for bit (same kernels).  Asynchronous. */
+size_t hrd_dirac_static_scratch_bytes(void);
+hrd_status hrd_dirac_apply_static(const hrd_lattice *lat, hrd_rep rep, hrd_prec prec,
+                                  const void *U, const void *psi, void *out, double m0,
+                                  hrd_parity parity, int dagger, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Level-1 linear algebra on packed spinors (the building blocks of the
