@@ -333,7 +333,7 @@ def cpu_oracle_configs(inputs, U48, psi48, m0_48, with_cg=True):
             r["cg"] = {"impl": "oracle.cg (numpy)", "seconds": time.perf_counter() - t0, **info}
         if with_cg and name == "c2_32^4_adj":
             t0 = time.perf_counter()
-            _, info = O.cg_native(U, psi_e, m0, 1e-10)
+            _, info = O.cg_native(U, psi_e, m0, 1e-10, progress=20)
             r["cg"] = {"impl": "oracle.cg_native (C)", "seconds": time.perf_counter() - t0, **info}
         out[name] = r
         del U, psi, psi_e
@@ -355,7 +355,7 @@ def oracle_solution_errors(U48, b48, m0, sols, tol=1e-12):
     import oracle as O
 
     t0 = time.perf_counter()
-    x_orc, info = O.cg_native(U48, b48, m0, tol)
+    x_orc, info = O.cg_native(U48, b48, m0, tol, progress=20)
     out = {"oracle_cg": {"tol": tol, "seconds": time.perf_counter() - t0, **info}, "solutions": {}}
     nx = np.linalg.norm(x_orc)
     for key, x in sols.items():

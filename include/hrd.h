@@ -273,6 +273,22 @@ int hrd_sun_rep_format(int nc, int kind);
 hrd_status hrd_represent_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind, const void *U_fund,
                              void *U_rep, void *stream);
 
+/* Chain rule of hrd_represent_sun, so that a derivative taken with respect to
+   the links of a representation (hrd_dirac_force on those links) reaches the
+   fundamental SU(nc) links (the HMC force of Sec. 2.1 for fermions in the
+   representations of Sec. 1).  G_rep: packed FP64 field in the format of the
+   representation, a derivative G = dL/dRe R + i dL/dIm R (real for the
+   adjoint); U_fund: the packed FP64 fundamental field (HRD_CPLX3 or
+   HRD_CPLX4) the representation was built from; G_fund (same format as
+   U_fund) receives dL/dRe U + i dL/dIm U, i.e. for L = Re sum conj(G_rep)
+   R(U): FUND G_rep itself, ADJ 4 sum_ab G_ab T_a U T_b, SYM and ASYM
+   2 sum_kl G_kl E_k conj(U) E_l^T (bases of hrd_represent_sun).  No overlap
+   of G_fund with the inputs (HRD_EALIAS); HRD_EINVAL for an (nc, kind)
+   without a format.  Asynchronous. */
+hrd_status hrd_represent_backward_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind,
+                                      const void *U_fund, const void *G_rep, void *G_fund,
+                                      void *stream);
+
 /* Chain rule through the adjoint map: given the packed FP64 fundamental field
    U_fund and a packed FP64 ADJ field g = dL/dR (real), writes the packed FP64
    FUND field G_fund = dL/dRe U + i dL/dIm U = sum_ab g_ab s_a U s_b. */

@@ -59,7 +59,7 @@ def _load():
         lib.oracle_plaquette.restype = ctypes.c_double
         lib.oracle_clover.argtypes = [P, ctypes.c_int, P, ctypes.c_double, P]
         lib.oracle_cg.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                  ctypes.POINTER(ctypes.c_double)]
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int]
         lib.oracle_cg.restype = ctypes.c_int
         lib.oracle_true_residual.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_double]
         lib.oracle_true_residual.restype = ctypes.c_double
@@ -232,10 +232,10 @@ def cg(U, b_e, m0, tol=1e-10, maxiter=10000, x0=None, op=None):
     return x, {"iters": iters, "true_rel_residual": res, "seconds": time.perf_counter() - t0}
 
 
-def cg_native(U, b_e, m0, tol=1e-10, maxiter=10000):
+def cg_native(U, b_e, m0, tol=1e-10, maxiter=10000, progress=0):
     """The iteration of cg() (x0 = 0, default operator) run entirely in the C
     part, for lattices where the numpy version is too slow.  Returns (x, info)
-    like cg()."""
+    like cg(); progress > 0 prints the residual every `progress` iterations."""
     dims = _dims_of_spinor(b_e)
     n = b_e.shape[-1]
     b = _cplx(b_e)
@@ -243,7 +243,7 @@ def cg_native(U, b_e, m0, tol=1e-10, maxiter=10000):
     res = ctypes.c_double(0.0)
     t0 = time.perf_counter()
     it = _load().oracle_cg(_ptr(_dims_arr(dims)), n, _ptr(_links_complex(U)), _ptr(b), _ptr(x), float(m0),
-                           float(tol), int(maxiter), ctypes.byref(res))
+                           float(tol), int(maxiter), ctypes.byref(res), int(progress))
     if it < 0:
         raise MemoryError("oracle_cg: temporaries could not be allocated")
     return x, {"iters": it, "true_rel_residual": res.value, "seconds": time.perf_counter() - t0}
@@ -533,3 +533,31 @@ def represent(U, rep):
         return R.real.copy()
     E = two_index_basis(nc, rep)
     return np.einsum("kji,...jm,lmn,...in->...kl", np.conj(E), U, E, U)
+
+
+def represent_backward(U, G, rep):
+    """Chain rule of represent(): for L(U) = Re sum conj(G) R(U) (for the real
+    adjoint, L = sum G R(U)), return dL/dRe U + i dL/dIm U [..., nc, nc], the
+    derivative convention of force().  Evaluated by reverse-mode automatic
+    differentiation (torch, CPU, complex128) of the representation map as
+    represent() defines it, so it shares no hand-written derivative with the
+    GPU library."""
+    import torch
+
+    U = _cplx(U)
+    nc = U.shape[-1]
+    Ut = torch.tensor(U, dtype=torch.complex128, requires_grad=True)
+    if rep == "fund":
+        R = Ut
+    elif rep == "adj":
+        T = torch.tensor(su_generators(nc))
+        Ud = torch.conj(Ut).transpose(-1, -2)
+        R = 2.0 * torch.einsum("aij,...jk,bkl,...li->...ab", T, Ut, T, Ud).real
+    else:
+        E = torch.tensor(two_index_basis(nc, rep))
+        R = torch.einsum("kji,...jm,lmn,...in->...kl", torch.conj(E), Ut, E, Ut)
+    Gt = torch.tensor(np.asarray(G))
+    L = (Gt.real * R).sum() if rep == "adj" else torch.real(torch.conj(Gt) * R).sum()
+    L.backward()
+    # torch's gradient of a real function of complex inputs is conj(dL/dz*) * 2 / 2 = dL/dRe + i dL/dIm
+    return Ut.grad.detach().numpy().copy()

@@ -31,6 +31,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -437,7 +438,9 @@ void oracle_clover(const int *d, int n, const cplx *U, double csw, cplx *A)
  * the recursively updated ||r|| <= tol ||b||, then recompute b - A x and go on
  * from it if that check fails.  Fields are full-lattice arrays [V][4][n]
  * whose odd sites are ignored on input and zero on output.  Returns the
- * iteration count; *res receives the final ||b - A x|| / ||b||.  Uses
+ * iteration count; *res receives the final ||b - A x|| / ||b||.  With
+ * progress > 0 it prints the iterated residual to stderr every `progress`
+ * iterations.  Uses
  * 7 temporary full-lattice fields from the heap; returns -1 if they cannot
  * be allocated.
  */
@@ -514,7 +517,7 @@ static double re_inner(long N, const cplx *a, const cplx *b)
 }
 
 int oracle_cg(const int *d, int n, const cplx *U, const cplx *b_in, cplx *x, double m0, double tol, int maxiter,
-              double *res)
+              double *res, int progress)
 {
     const long V = volume(d);
     const long N = V * 4 * n;
@@ -560,6 +563,10 @@ int oracle_cg(const int *d, int n, const cplx *U, const cplx *b_in, cplx *x, dou
         for (long k = 0; k < N; k++) p[k] = r[k] + beta * p[k];
         rr = rr_new;
         it++;
+        if (progress > 0 && it % progress == 0) {
+            fprintf(stderr, "[oracle cg] iteration %d, ||r||/||b|| = %.3e\n", it, sqrt(rr) / bnorm);
+            fflush(stderr);
+        }
     }
     normal_even(d, n, U, x, Ap, t1, t2, t3, m0);
 #pragma omp parallel for schedule(static)

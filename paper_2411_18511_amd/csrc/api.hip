@@ -407,6 +407,22 @@ hrd_status hrd_represent_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind, c
                      "represent_sun launch");
 }
 
+hrd_status hrd_represent_backward_sun(const hrd_lattice *lat, int nc, hrd_sun_rep kind, const void *U_fund,
+                                      const void *G_rep, void *G_fund, void *stream)
+{
+    HRD_TRY(check_lattice(lat));
+    const int rf = hrd_sun_rep_format(nc, kind);
+    if (rf < 0) return fail(HRD_EINVAL, "no link format for SU(%d) representation %d", nc, (int)kind);
+    if (!U_fund || !G_rep || !G_fund) return fail(HRD_EINVAL, "NULL field pointer");
+    const int in = nc == 3 ? HRD_CPLX3 : HRD_CPLX4;
+    const size_t nf = gauge_bytes(lat, in, HRD_F64), nr = gauge_bytes(lat, rf, HRD_F64);
+    if (overlap(G_fund, nf, U_fund, nf) || overlap(G_fund, nf, G_rep, nr))
+        return fail(HRD_EALIAS, "output overlaps input");
+    const Geom g = make_geom(lat->dims);
+    return check_hip(launch_represent_backward_sun(nc, (int)kind, g, U_fund, G_rep, G_fund, (hipStream_t)stream),
+                     "represent_backward_sun launch");
+}
+
 hrd_status hrd_represent_backward(const hrd_lattice *lat, const void *U_fund, const void *g_adj, void *G_fund,
                                   void *stream)
 {

@@ -59,6 +59,10 @@ hipError_t launch_pack_gauge_dense(int rep, int prec, const Geom &g, const void 
                                    hipStream_t st);
 hipError_t launch_convert_gauge_dense(int rep, int prec_out, const Geom &g, const void *U64, void *Uout,
                                       hipStream_t st);
+// chain rule of launch_represent_sun: G_rep (format of the representation,
+// FP64) -> G_fund (CPLXnc, FP64)
+hipError_t launch_represent_backward_sun(int nc, int kind, const Geom &g, const void *Uf, const void *Gr, void *Gf,
+                                         hipStream_t st);
 hipError_t launch_represent_sun(int nc, int kind, const Geom &g, const void *Uf, void *Ur, hipStream_t st);
 // F64 links -> F16 links
 hipError_t launch_convert_gauge_h16(int rep, const Geom &g, const void *U64, void *U16, hipStream_t st);

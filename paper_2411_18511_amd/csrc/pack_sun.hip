@@ -201,6 +201,86 @@ __global__ __launch_bounds__(64) void represent_sun_kernel(Geom g, const void *U
     }
 }
 
+// Two-index basis element k as a dense matrix: e_c e_c^T, or
+// (e_c e_d^T +- e_d e_c^T)/sqrt(2) for the pair (c, d) of basis_pair.
+template <int NC, bool SYM>
+__device__ Mat<NC> two_index_element(int k)
+{
+    Mat<NC> e;
+    for (int i = 0; i < NC; i++)
+        for (int j = 0; j < NC; j++) e.m[i][j] = Cx<double>{0.0, 0.0};
+    int c, d;
+    basis_pair<NC, SYM>(k, c, d);
+    const double r2 = 0.70710678118654752440;  // 1/sqrt(2)
+    if (c == d) {
+        e.m[c][c] = Cx<double>{1.0, 0.0};
+    } else {
+        e.m[c][d] = Cx<double>{r2, 0.0};
+        e.m[d][c] = Cx<double>{SYM ? r2 : -r2, 0.0};
+    }
+    return e;
+}
+
+// Chain rule of represent_sun_kernel: for L = Re sum conj(G) R(U) (real
+// adjoint: L = sum G R(U)), Gf = dL/dRe U + i dL/dIm U:
+//   fundamental: G;
+//   adjoint:     R_ab = 2 tr(T_a U T_b U^+) gives 4 sum_ab G_ab T_a U T_b;
+//   two-index:   R_kl = tr(E_k^T U E_l U^T) (E real, E^T = +-E) gives
+//                dR_kl/dU = 2 E_k U E_l^T, so 2 sum_kl G_kl E_k conj(U) E_l^T.
+template <int NC, int KIND, int RF>
+__global__ __launch_bounds__(64) void represent_backward_sun_kernel(Geom g, const void *Uf, const void *Gr, void *Gf)
+{
+    constexpr int D = ncolour(RF);
+    const long t = (long)blockIdx.x * 64 + threadIdx.x;
+    if (t >= 8L * g.Vh) return;
+    const int pm = (int)(t / g.Vh);
+    const int idx = (int)(t - (long)pm * g.Vh);
+    const int p = pm >> 2, mu = pm & 3;
+    CLink<NC, double> out;
+    if constexpr (KIND == 0) {
+        out = CplxIO<NC, double>::load(Gr, g.Vh, p, mu, idx);
+    } else {
+        const auto f = CplxIO<NC, double>::load(Uf, g.Vh, p, mu, idx);
+        Mat<NC> M, acc;  // M = U (adjoint) or conj(U) (two-index)
+        for (int i = 0; i < NC; i++)
+            for (int j = 0; j < NC; j++) {
+                M.m[i][j] = KIND == 1 ? f.u[i][j] : Cx<double>{f.u[i][j].re, -f.u[i][j].im};
+                acc.m[i][j] = Cx<double>{0.0, 0.0};
+            }
+        const auto G = LinkIO<RF, double>::load(Gr, g.Vh, p, mu, idx);
+        for (int l = 0; l < D; l++) {
+            // P = M B_l with B_l = T_l (adjoint) or E_l^T (two-index)
+            Mat<NC> B;
+            if constexpr (KIND == 1) {
+                B = generator<NC>(l);
+            } else {
+                const Mat<NC> e = two_index_element<NC, KIND == 2>(l);
+                for (int i = 0; i < NC; i++)
+                    for (int j = 0; j < NC; j++) B.m[i][j] = e.m[j][i];
+            }
+            const Mat<NC> P = matmul(M, B);
+            // A = sum_k c_kl A_k, A_k = T_k or E_k, c_kl = 4 G_kl or 2 G_kl
+            Mat<NC> A;
+            for (int i = 0; i < NC; i++)
+                for (int j = 0; j < NC; j++) A.m[i][j] = Cx<double>{0.0, 0.0};
+            for (int k = 0; k < D; k++) {
+                const Mat<NC> Ak = KIND == 1 ? generator<NC>(k) : two_index_element<NC, KIND == 2>(k);
+                Cx<double> c;
+                if constexpr (KIND == 1) c = Cx<double>{4.0 * G.r[k][l], 0.0};
+                else c = Cx<double>{2.0 * G.u[k][l].re, 2.0 * G.u[k][l].im};
+                for (int i = 0; i < NC; i++)
+                    for (int j = 0; j < NC; j++) A.m[i][j] = cfma(c, Ak.m[i][j], A.m[i][j]);
+            }
+            const Mat<NC> AP = matmul(A, P);
+            for (int i = 0; i < NC; i++)
+                for (int j = 0; j < NC; j++) acc.m[i][j] = acc.m[i][j] + AP.m[i][j];
+        }
+        for (int i = 0; i < NC; i++)
+            for (int j = 0; j < NC; j++) out.u[i][j] = acc.m[i][j];
+    }
+    CplxIO<NC, double>::store(Gf, g.Vh, p, mu, idx, out);
+}
+
 template <typename S>
 void pack_dense_for(int rep, const Geom &g, void *nat, void *packed, bool unpack, hipStream_t st)
 {
@@ -262,6 +342,24 @@ hipError_t launch_represent_sun(int nc, int kind, const Geom &g, const void *Uf,
     } else {
         if (kind == 0) hipLaunchKernelGGL((represent_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Ur);
         else hipLaunchKernelGGL((represent_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Ur);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_represent_backward_sun(int nc, int kind, const Geom &g, const void *Uf, const void *Gr, void *Gf,
+                                        hipStream_t st)
+{
+    const dim3 grid((unsigned)((8L * g.Vh + 63) / 64)), block(64);
+    if (nc == 3) {
+        switch (kind) {
+            case 0: hipLaunchKernelGGL((represent_backward_sun_kernel<3, 0, HRD_CPLX3>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            case 1: hipLaunchKernelGGL((represent_backward_sun_kernel<3, 1, HRD_REAL8>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            case 2: hipLaunchKernelGGL((represent_backward_sun_kernel<3, 2, HRD_CPLX6>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            default: hipLaunchKernelGGL((represent_backward_sun_kernel<3, 3, HRD_CPLX3>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+        }
+    } else {
+        if (kind == 0) hipLaunchKernelGGL((represent_backward_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Gr, Gf);
+        else hipLaunchKernelGGL((represent_backward_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Gr, Gf);
     }
     return hipGetLastError();
 }

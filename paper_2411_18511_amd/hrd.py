@@ -126,6 +126,7 @@ _sig("hrd_represent", _I, _LP, _P, _P, _I, _P)
 _sig("hrd_represent_backward", _I, _LP, _P, _P, _P, _P)
 _sig("hrd_sun_rep_format", _I, _I, _I)
 _sig("hrd_represent_sun", _I, _LP, _I, _I, _P, _P, _P)
+_sig("hrd_represent_backward_sun", _I, _LP, _I, _I, _P, _P, _P, _P)
 _sig("hrd_convert_gauge", _I, _LP, _I, _P, _P, _P)
 _sig("hrd_pack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
 _sig("hrd_unpack_spinor", _I, _LP, _I, _I, _I, _P, _P, _P)
@@ -299,6 +300,20 @@ def represent_sun(U_fund64, dims, nc, kind):
     out = _empty(gauge_bytes(dims, fmt, F64), U_fund64.device)
     _check(_lib.hrd_represent_sun(ctypes.byref(lattice(dims)), int(nc), _SUN_KINDS[kind], _ptr(U_fund64), _ptr(out),
                                   _stream()))
+    return out
+
+
+def represent_backward_sun(U_fund64, G_rep, dims, nc, kind):
+    """Packed FP64 fundamental derivative (format CPLX3 / CPLX4) from a packed
+    FP64 derivative with respect to the links of representation kind of SU(nc)
+    (chain rule of represent_sun)."""
+    fmt = sun_rep_format(nc, kind)
+    if fmt is None:
+        raise ValueError(f"no link format for SU({nc}) {kind}")
+    _need(G_rep, gauge_bytes(dims, fmt, F64), "G_rep")
+    out = _empty(gauge_bytes(dims, CPLX3 if nc == 3 else CPLX4, F64), U_fund64.device)
+    _check(_lib.hrd_represent_backward_sun(ctypes.byref(lattice(dims)), int(nc), _SUN_KINDS[kind], _ptr(U_fund64),
+                                           _ptr(G_rep), _ptr(out), _stream()))
     return out
 
 

@@ -13,7 +13,8 @@ CPLX4, CPLX6 and REAL8.
   recomputation);
 * the force d/dU Re<X, D[U] Y> and the action force with respect to the
   representation's links equal the oracle's to 1e-13 (real part for the
-  real adjoint links).
+  real adjoint links); the chain rule of the representation map takes them
+  to the fundamental links (oracle: automatic differentiation of its map).
 """
 import numpy as np
 import pytest
@@ -226,3 +227,50 @@ def test_su3_two_row_format(oracle, dims):
     G = h.unpack_gauge(h.dirac_force(U64, Xp, Yp, dims, "su3_row2"), dims, "cplx3", "f64").cpu().numpy()
     wantG = oracle.force(X, Y)
     assert np.abs(G.reshape(wantG.shape) - wantG).max() <= 1e-13 * np.abs(wantG).max()
+
+
+@pytest.mark.parametrize("nc,rep", CASES)
+def test_represent_backward_sun(oracle, nc, rep):
+    """Chain rule of the representation map on the GPU against the oracle's
+    (automatic differentiation of its own map), for an arbitrary derivative
+    G_rep, and the action force carried to the fundamental links: the GPU's
+    dS/dR (action_force on the representation's links) through
+    represent_backward_sun against the oracle's dS/dR through its chain rule."""
+    h = hrd()
+    dims, m0 = (4, 2, 4, 6), -0.3
+    F = FieldSUN(dims, nc, rep, seed=61)
+    real = F.fmt == h.REAL8
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(62)
+    shape = (4,) + dims + (F.n, F.n)
+    Gr = rng.standard_normal(shape) + (0 if real else 1j) * rng.standard_normal(shape)
+    Uf64 = h.pack_gauge(to_dev_gauge(F.Uf), dims, "cplx3" if nc == 3 else "cplx4", "f64")
+    nat = torch.from_numpy(np.ascontiguousarray(Gr.real if real else Gr).reshape(4, V, F.n, F.n)).cuda()
+    Gf = h.represent_backward_sun(Uf64, h.pack_gauge(nat, dims, F.fmt, "f64"), dims, nc, rep)
+    fund = "cplx3" if nc == 3 else "cplx4"
+    got = h.unpack_gauge(Gf, dims, fund, "f64").cpu().numpy().reshape((4,) + dims + (nc, nc))
+    want = oracle.represent_backward(F.Uf, Gr, rep)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # dS/dU for S = phi^+ (D^+ D^)^-1 phi with the fermions in representation rep
+    xi = oracle.restrict(F.spinor(63), 0)
+    GR = h.action_force(F.U64, F.pack(xi, "f64", "even"), m0, dims, F.fmt)
+    Gf = h.represent_backward_sun(Uf64, GR, dims, nc, rep)
+    got = h.unpack_gauge(Gf, dims, fund, "f64").cpu().numpy().reshape((4,) + dims + (nc, nc))
+    Xa, Ya = oracle.action_force_fields(F.U_orc, xi, m0)
+    GR_orc = (2.0 / (4 + m0)) * oracle.force(Xa, Ya, real_links=real)
+    want = oracle.represent_backward(F.Uf, GR_orc, rep)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_represent_backward_sun_errors():
+    h = hrd()
+    dims = (4, 4, 4, 4)
+    F = FieldSUN(dims, 3, "adj", seed=64)
+    Uf64 = h.pack_gauge(to_dev_gauge(F.Uf), dims, "cplx3", "f64")
+    with pytest.raises(ValueError):
+        h.represent_backward_sun(Uf64, F.U64, dims, 4, "sym")  # no SU(4) symmetric format yet
+    import ctypes
+
+    st = h._lib.hrd_represent_backward_sun(ctypes.byref(h.lattice(dims)), 3, 1, Uf64.data_ptr(), F.U64.data_ptr(),
+                                           Uf64.data_ptr(), None)
+    assert st == h.EALIAS

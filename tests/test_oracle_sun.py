@@ -122,3 +122,40 @@ def test_gamma5_and_covariance(oracle, nc, rep):
     want = np.einsum("...ij,...aj->...ai", gR, oracle.dirac(U, psi, m0))
     assert np.abs(lhs - want).max() < 1e-12
     assert np.abs(oracle.dirac(U, gpsi, m0) - want).max() > 1e-3
+
+
+def _links_sun(nc, shape, seed):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(shape + (nc, nc)) + 1j * rng.standard_normal(shape + (nc, nc))
+    q, r = np.linalg.qr(z)
+    q = q * (np.diagonal(r, axis1=-2, axis2=-1) / np.abs(np.diagonal(r, axis1=-2, axis2=-1)))[..., None, :]
+    d = np.linalg.det(q)
+    return q / (d ** (1.0 / nc))[..., None, None]
+
+
+@pytest.mark.parametrize("nc,rep", [(3, "fund"), (3, "adj"), (3, "sym"), (3, "asym"), (4, "adj"), (4, "sym"),
+                                    (4, "asym")])
+def test_represent_backward_directional_derivative(oracle, nc, rep):
+    """The chain rule of represent() against central differences of
+    L(U) = Re sum conj(G) R(U) along random complex directions E (not tangent
+    to SU(nc): the derivative is that of the map on all matrices):
+    (L(U + eps E) - L(U - eps E)) / (2 eps) = Re sum conj(G_U) E, exact up to
+    O(eps^2) (R is quadratic in U), checked to 1e-8 at eps = 1e-5."""
+    rng = np.random.default_rng(100 + nc)
+    U = _links_sun(nc, (3,), 7)
+    d = oracle.rep_dim(nc, rep)
+    G = rng.standard_normal((3, d, d)) + (0 if rep == "adj" else 1j) * rng.standard_normal((3, d, d))
+    GU = oracle.represent_backward(U, G, rep)
+
+    def L(u):
+        R = oracle.represent(u, rep)
+        return float(np.sum(G.real * R)) if rep == "adj" else float(np.real(np.sum(np.conj(G) * R)))
+
+    for k in range(4):
+        E = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+        eps = 1e-5
+        fd = (L(U + eps * E) - L(U - eps * E)) / (2 * eps)
+        an = float(np.real(np.sum(np.conj(GU) * E)))
+        assert abs(fd - an) <= 1e-8 * max(1.0, abs(an)), (nc, rep, k, fd, an)
+    if rep == "fund":
+        assert np.array_equal(GU, G)
