@@ -88,6 +88,9 @@
  *                    (entries 2q, 2q+1); F16 ceil(n^2/4) planes of 4 complex
  *                    as 8 binary16 (entries 4q .. 4q+3).  Slots past the last
  *                    entry are padding (written as zero).
+ *     link REAL15 (15 x 15 real, entry e = 15 i + j): F64 113 planes of 2
+ *                    float64, F32 57 planes of 4 float32, F16 29 planes of 8
+ *                    binary16 (padding as for CPLXn).
  *     link REAL8 (8 x 8 real, entry e = 8 i + j): F64 32 planes of 2 float64,
  *                    F32 16 planes of 4 float32, F16 8 planes of 8 binary16.
  *     link SU3_ROW2 (rows 0 and 1 of an SU(3) link, entries U00 U01 U02 U10
@@ -103,7 +106,8 @@
  *   spinor : complex128 [V][4][N]          (site lex, spin, colour)
  *   gauge  : complex128 [4][V][2][2] FUND, FUND_SU2 and ADJ_SU2 (the
  *            fundamental links), float64 [4][V][3][3] ADJ, complex128
- *            [4][V][n][n] CPLXn, float64 [4][V][8][8] REAL8
+ *            [4][V][n][n] CPLXn, float64 [4][V][8][8] REAL8, float64
+ *            [4][V][15][15] REAL15
  *
  * OWNERSHIP AND ERRORS
  *   Every field pointer is a device pointer owned by the caller; the library
@@ -163,6 +167,8 @@ typedef enum {
          HRD_CPLX6 : complex 6x6 (SU(3) 2-index symmetric, SU(4) 2-index
                      antisymmetric)
          HRD_REAL8 : real 8x8    (SU(3) adjoint)
+         HRD_CPLX10: complex 10x10 (SU(4) 2-index symmetric)
+         HRD_REAL15: real 15x15  (SU(4) adjoint)
        hrd_represent_sun builds them from fundamental SU(N) links. */
     HRD_CPLX3 = 4,
     HRD_CPLX4 = 5,
@@ -170,7 +176,9 @@ typedef enum {
     HRD_REAL8 = 7,
     /* SU(3) fundamental links stored as their first two rows; the third row
        is conj(row0 x row1), exact for SU(3) matrices (assumed). */
-    HRD_SU3_ROW2 = 8
+    HRD_SU3_ROW2 = 8,
+    HRD_CPLX10 = 9,
+    HRD_REAL15 = 10
 } hrd_rep;
 /* Storage precision of a field.  HRD_F16 is the 16-bit storage of the mixed
    solver's inner iterations (binary16 values, FP32 arithmetic; spinors carry
@@ -253,7 +261,8 @@ hrd_status hrd_represent(const hrd_lattice *lat, const void *U_fund, void *U_adj
 /* Representations of SU(N > 2) (Sec. 1).  kind selects the representation;
    hrd_sun_rep_format returns the link format of (nc, kind), or -1 when none
    exists:  SU(3): FUND -> HRD_CPLX3, ADJ -> HRD_REAL8, SYM -> HRD_CPLX6,
-   ASYM -> HRD_CPLX3;  SU(4): FUND -> HRD_CPLX4, ASYM -> HRD_CPLX6.  (SU(3)
+   ASYM -> HRD_CPLX3;  SU(4): FUND -> HRD_CPLX4, ADJ -> HRD_REAL15,
+   SYM -> HRD_CPLX10, ASYM -> HRD_CPLX6.  (SU(3)
    fundamental links may also be packed directly as HRD_SU3_ROW2.)
    Bases: ADJ R_ab = 2 Re tr(T_a U T_b U^+) with T_a the generalised Gell-Mann
    matrices halved, ordered pairwise (j < k: symmetric then antisymmetric)

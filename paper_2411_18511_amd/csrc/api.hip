@@ -63,7 +63,7 @@ hrd_status check_rep_prec_any(hrd_rep rep, hrd_prec prec)
 
 hrd_status check_rep_prec(hrd_rep rep, hrd_prec prec)
 {
-    if (rep < HRD_FUND || rep > HRD_SU3_ROW2) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
+    if (rep < HRD_FUND || rep > HRD_REAL15) return fail(HRD_EINVAL, "invalid representation %d", (int)rep);
     if (prec != HRD_F64 && prec != HRD_F32) return fail(HRD_EINVAL, "invalid precision %d", (int)prec);
     return HRD_OK;
 }
@@ -386,8 +386,13 @@ int hrd_sun_rep_format(int nc, int kind)
         }
     }
     if (nc == 4) {
-        if (kind == HRD_SUN_FUND) return HRD_CPLX4;
-        if (kind == HRD_SUN_ASYM) return HRD_CPLX6;
+        switch (kind) {
+            case HRD_SUN_FUND: return HRD_CPLX4;
+            case HRD_SUN_ADJ: return HRD_REAL15;
+            case HRD_SUN_SYM: return HRD_CPLX10;
+            case HRD_SUN_ASYM: return HRD_CPLX6;
+            default: return -1;
+        }
     }
     return -1;
 }

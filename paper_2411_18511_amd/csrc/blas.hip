@@ -476,7 +476,9 @@ void launch_ring_h16(int Vh, int ncomp, void *x64, char *ring, size_t stride, in
         case 12: HRD_RING16(12); break;
         case 16: HRD_RING16(16); break;
         case 24: HRD_RING16(24); break;
-        default: HRD_RING16(32); break;
+        case 32: HRD_RING16(32); break;
+        case 40: HRD_RING16(40); break;
+        default: HRD_RING16(60); break;
     }
 #undef HRD_RING16
 }

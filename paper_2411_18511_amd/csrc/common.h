@@ -474,12 +474,14 @@ __host__ __device__ constexpr int ncolour(int rep)
            : (rep == HRD_ADJ || rep == HRD_ADJ_SU2 || rep == HRD_CPLX3 || rep == HRD_SU3_ROW2) ? 3
            : rep == HRD_CPLX4 ? 4
            : rep == HRD_CPLX6 ? 6
+           : rep == HRD_CPLX10 ? 10
+           : rep == HRD_REAL15 ? 15
            : 8;
 }
 
 // Dense link formats of SU(N > 2) representations.
 __host__ __device__ constexpr bool is_dense(int rep) { return rep >= HRD_CPLX3; }
-__host__ __device__ constexpr bool is_real_dense(int rep) { return rep == HRD_REAL8; }
+__host__ __device__ constexpr bool is_real_dense(int rep) { return rep == HRD_REAL8 || rep == HRD_REAL15; }
 // Formats the clover term supports: the SU(2) ones and SU(3) fundamental links.
 __host__ __device__ constexpr bool clover_capable(int rep)
 {
@@ -1161,6 +1163,10 @@ template <typename S>
 struct LinkIO<HRD_CPLX6, S> : CplxIO<6, S> {};
 template <typename S>
 struct LinkIO<HRD_REAL8, S> : RealIO<8, S> {};
+template <typename S>
+struct LinkIO<HRD_CPLX10, S> : CplxIO<10, S> {};
+template <typename S>
+struct LinkIO<HRD_REAL15, S> : RealIO<15, S> {};
 
 template <int N, typename R>
 __device__ __forceinline__ void link_mul(const CLink<N, R> &l, const Cx<R> (&h)[N], Cx<R> (&o)[N])

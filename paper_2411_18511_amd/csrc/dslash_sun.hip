@@ -18,6 +18,8 @@ hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool n
         case HRD_CPLX3: return dispatch_hop_clov<HRD_CPLX3, S>(a, dag, has_a, norm, full, st, clov);
         case HRD_CPLX4: return dispatch_hop<HRD_CPLX4, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
         case HRD_CPLX6: return dispatch_hop<HRD_CPLX6, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
+        case HRD_CPLX10: return dispatch_hop<HRD_CPLX10, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
+        case HRD_REAL15: return dispatch_hop<HRD_REAL15, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
         case HRD_SU3_ROW2: return dispatch_hop_clov<HRD_SU3_ROW2, S>(a, dag, has_a, norm, full, st, clov);
         default: return dispatch_hop<HRD_REAL8, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
     }
@@ -32,6 +34,8 @@ hipError_t dense_rupd_for(int rep, const HopArgs &a, hipStream_t st, int clov)
         case HRD_CPLX3: return dispatch_rupd<HRD_CPLX3, S>(a, st, clov);
         case HRD_CPLX4: return dispatch_rupd<HRD_CPLX4, S>(a, st, CLOV_NONE);
         case HRD_CPLX6: return dispatch_rupd<HRD_CPLX6, S>(a, st, CLOV_NONE);
+        case HRD_CPLX10: return dispatch_rupd<HRD_CPLX10, S>(a, st, CLOV_NONE);
+        case HRD_REAL15: return dispatch_rupd<HRD_REAL15, S>(a, st, CLOV_NONE);
         case HRD_SU3_ROW2: return dispatch_rupd<HRD_SU3_ROW2, S>(a, st, clov);
         default: return dispatch_rupd<HRD_REAL8, S>(a, st, CLOV_NONE);
     }

@@ -8,7 +8,7 @@
 // with h the upper half of (1 + SIG g_mu) applied to the field.
 // One thread per site computes the four links leaving it; every output link
 // has exactly one writer (no atomics).  For the dense SU(N > 2) formats the
-// derivative is written in the format itself (real part only for REAL8).
+// derivative is written in the format itself (real part only for REAL8 and REAL15).
 #include "kernels.h"
 #include "spin.h"
 
@@ -49,25 +49,26 @@ __device__ __forceinline__ void force_dir(const Geom &g, const Site &s, int idx,
     };
     if constexpr (is_dense(REP)) {
         // dense formats, FP64 layout: entry e = N i + k in plane e (CPLXn:
-        // one complex per plane; REAL8: two reals per plane), rows stored
-        // as they are formed
+        // one complex per plane) or in slot e % 2 of plane e / 2 (REALn: two
+        // reals per plane; a row of odd length ends inside a plane and the
+        // last plane of an odd entry count is padded with zero)
         char *blk = reinterpret_cast<char *>(F) +
                     (size_t)(4 * p + MU) * g.Vh * (size_t)link_bytes(REP, HRD_F64);
+        if constexpr (is_real_dense(REP)) {
 #pragma unroll
-        for (int i = 0; i < N; i++) {
-            if constexpr (is_real_dense(REP)) {
+            for (int e = 0; e < N * N; e += 2) {
+                const double v0 = entry(e / N, e % N).re;
+                const double v1 = e + 1 < N * N ? entry((e + 1) / N, (e + 1) % N).re : 0.0;
+                st16d<false>(blk + ((size_t)(e / 2) * g.Vh + idx) * 16, vd2{v0, v1});
+            }
+        } else {
 #pragma unroll
-                for (int k = 0; k < N; k += 2) {
-                    const int q = (N * i + k) / 2;
-                    st16d<false>(blk + ((size_t)q * g.Vh + idx) * 16, vd2{entry(i, k).re, entry(i, k + 1).re});
-                }
-            } else {
+            for (int i = 0; i < N; i++)
 #pragma unroll
                 for (int k = 0; k < N; k++) {
                     const Cx<double> z = entry(i, k);
                     st16d<false>(blk + ((size_t)(N * i + k) * g.Vh + idx) * 16, vd2{z.re, z.im});
                 }
-            }
         }
     } else {
         Cx<double> G[N][N];
@@ -128,6 +129,8 @@ hipError_t launch_force(int rep, const Geom &g, const void *X, const void *Y, vo
         case HRD_CPLX3: hipLaunchKernelGGL(force_kernel<HRD_CPLX3>, grid, block, 0, st, g, x, y, F, scale); break;
         case HRD_CPLX4: hipLaunchKernelGGL(force_kernel<HRD_CPLX4>, grid, block, 0, st, g, x, y, F, scale); break;
         case HRD_CPLX6: hipLaunchKernelGGL(force_kernel<HRD_CPLX6>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_CPLX10: hipLaunchKernelGGL(force_kernel<HRD_CPLX10>, grid, block, 0, st, g, x, y, F, scale); break;
+        case HRD_REAL15: hipLaunchKernelGGL(force_kernel<HRD_REAL15>, grid, block, 0, st, g, x, y, F, scale); break;
         default: hipLaunchKernelGGL(force_kernel<HRD_REAL8>, grid, block, 0, st, g, x, y, F, scale); break;
     }
     return hipGetLastError();

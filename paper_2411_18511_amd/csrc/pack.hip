@@ -364,7 +364,9 @@ hipError_t launch_pack_spinor(int rep, int prec, int sites, const Geom &g, const
         case 3: pack_spinor_n<3>(prec, grid, st, g, p0, np, n, pk, unpack); break;
         case 4: pack_spinor_n<4>(prec, grid, st, g, p0, np, n, pk, unpack); break;
         case 6: pack_spinor_n<6>(prec, grid, st, g, p0, np, n, pk, unpack); break;
-        default: pack_spinor_n<8>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        case 8: pack_spinor_n<8>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        case 10: pack_spinor_n<10>(prec, grid, st, g, p0, np, n, pk, unpack); break;
+        default: pack_spinor_n<15>(prec, grid, st, g, p0, np, n, pk, unpack); break;
     }
     return hipGetLastError();
 }
@@ -485,7 +487,9 @@ hipError_t launch_convert_spinor_prec(int rep, int Vh, int nparity, int prec_in,
         case 3: convert_nc<12>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
         case 4: convert_nc<16>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
         case 6: convert_nc<24>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
-        default: convert_nc<32>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case 8: convert_nc<32>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        case 10: convert_nc<40>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
+        default: convert_nc<60>(prec_in, prec_out, Vh, nparity, ib, ob, in, out, st); break;
     }
     return hipGetLastError();
 }

@@ -289,6 +289,8 @@ void pack_dense_for(int rep, const Geom &g, void *nat, void *packed, bool unpack
         case HRD_CPLX3: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX3, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         case HRD_CPLX4: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX4, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         case HRD_CPLX6: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX6, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
+        case HRD_CPLX10: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_CPLX10, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
+        case HRD_REAL15: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_REAL15, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         case HRD_SU3_ROW2: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_SU3_ROW2, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
         default: hipLaunchKernelGGL((pack_gauge_dense_kernel<HRD_REAL8, S>), grid, dim3(kBlock), 0, st, g, nat, packed, unpack); break;
     }
@@ -302,6 +304,8 @@ void convert_dense_for(int rep, const Geom &g, const void *U64, void *Uout, hipS
         case HRD_CPLX3: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX3, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         case HRD_CPLX4: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX4, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         case HRD_CPLX6: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX6, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
+        case HRD_CPLX10: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_CPLX10, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
+        case HRD_REAL15: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_REAL15, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         case HRD_SU3_ROW2: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_SU3_ROW2, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
         default: hipLaunchKernelGGL((convert_gauge_dense_kernel<HRD_REAL8, SO>), grid, dim3(kBlock), 0, st, g, U64, Uout); break;
     }
@@ -340,8 +344,12 @@ hipError_t launch_represent_sun(int nc, int kind, const Geom &g, const void *Uf,
             default: hipLaunchKernelGGL((represent_sun_kernel<3, 3, HRD_CPLX3>), grid, block, 0, st, g, Uf, Ur); break;
         }
     } else {
-        if (kind == 0) hipLaunchKernelGGL((represent_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Ur);
-        else hipLaunchKernelGGL((represent_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Ur);
+        switch (kind) {
+            case 0: hipLaunchKernelGGL((represent_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Ur); break;
+            case 1: hipLaunchKernelGGL((represent_sun_kernel<4, 1, HRD_REAL15>), grid, block, 0, st, g, Uf, Ur); break;
+            case 2: hipLaunchKernelGGL((represent_sun_kernel<4, 2, HRD_CPLX10>), grid, block, 0, st, g, Uf, Ur); break;
+            default: hipLaunchKernelGGL((represent_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Ur); break;
+        }
     }
     return hipGetLastError();
 }
@@ -358,8 +366,12 @@ hipError_t launch_represent_backward_sun(int nc, int kind, const Geom &g, const 
             default: hipLaunchKernelGGL((represent_backward_sun_kernel<3, 3, HRD_CPLX3>), grid, block, 0, st, g, Uf, Gr, Gf); break;
         }
     } else {
-        if (kind == 0) hipLaunchKernelGGL((represent_backward_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Gr, Gf);
-        else hipLaunchKernelGGL((represent_backward_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Gr, Gf);
+        switch (kind) {
+            case 0: hipLaunchKernelGGL((represent_backward_sun_kernel<4, 0, HRD_CPLX4>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            case 1: hipLaunchKernelGGL((represent_backward_sun_kernel<4, 1, HRD_REAL15>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            case 2: hipLaunchKernelGGL((represent_backward_sun_kernel<4, 2, HRD_CPLX10>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+            default: hipLaunchKernelGGL((represent_backward_sun_kernel<4, 3, HRD_CPLX6>), grid, block, 0, st, g, Uf, Gr, Gf); break;
+        }
     }
     return hipGetLastError();
 }

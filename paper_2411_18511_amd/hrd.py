@@ -42,7 +42,7 @@ _check_build()
 # enums (hrd.h)
 OK, EINVAL, ESHAPE, EALIAS, EHIP, ENOCONV, EBREAKDOWN, ESIZE = range(8)
 FUND, ADJ, FUND_SU2, ADJ_SU2 = 0, 1, 2, 3
-CPLX3, CPLX4, CPLX6, REAL8, SU3_ROW2 = 4, 5, 6, 7, 8
+CPLX3, CPLX4, CPLX6, REAL8, SU3_ROW2, CPLX10, REAL15 = 4, 5, 6, 7, 8, 9, 10
 SUN_FUND, SUN_ADJ, SUN_SYM, SUN_ASYM = 0, 1, 2, 3
 F64, F32, F16 = 0, 1, 2
 FULL, EO, HOP_EO, HOP_OE = 0, 1, 2, 3
@@ -52,12 +52,13 @@ CG_F64, CG_MIXED, CG_MIXED16 = 0, 1, 2
 _STATUS_NAMES = {0: "HRD_OK", 1: "HRD_EINVAL", 2: "HRD_ESHAPE", 3: "HRD_EALIAS", 4: "HRD_EHIP",
                  5: "HRD_ENOCONV", 6: "HRD_EBREAKDOWN", 7: "HRD_ESIZE"}
 _REPS = {"fund": FUND, "fundamental": FUND, "adj": ADJ, "adjoint": ADJ, "fund_su2": FUND_SU2,
-         "adj_su2": ADJ_SU2, "cplx3": CPLX3, "cplx4": CPLX4, "cplx6": CPLX6, "real8": REAL8,
+         "adj_su2": ADJ_SU2, "cplx3": CPLX3, "cplx4": CPLX4, "cplx6": CPLX6, "real8": REAL8, "cplx10": CPLX10,
+         "real15": REAL15,
          # SU(N > 2) representations by name -> their link formats
          "su3_fund": CPLX3, "su3_asym": CPLX3, "su3_sym": CPLX6, "su3_adj": REAL8, "su4_fund": CPLX4,
-         "su4_asym": CPLX6, "su3_row2": SU3_ROW2,
+         "su4_asym": CPLX6, "su3_row2": SU3_ROW2, "su4_sym": CPLX10, "su4_adj": REAL15,
          FUND: FUND, ADJ: ADJ, FUND_SU2: FUND_SU2, ADJ_SU2: ADJ_SU2, CPLX3: CPLX3, CPLX4: CPLX4, CPLX6: CPLX6,
-         REAL8: REAL8, SU3_ROW2: SU3_ROW2}
+         REAL8: REAL8, SU3_ROW2: SU3_ROW2, CPLX10: CPLX10, REAL15: REAL15}
 _SUN_KINDS = {"fund": SUN_FUND, "adj": SUN_ADJ, "sym": SUN_SYM, "asym": SUN_ASYM}
 _PRECS = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32, "f16": F16, "fp16": F16, F64: F64, F32: F32,
           F16: F16, torch.float64: F64, torch.float32: F32}
@@ -231,7 +232,8 @@ class Geometry:
 
 def ncolour(rep):
     """Colours of the fermion in a link format (2, 3, 4, 6 or 8)."""
-    return {FUND: 2, FUND_SU2: 2, ADJ: 3, ADJ_SU2: 3, CPLX3: 3, CPLX4: 4, CPLX6: 6, REAL8: 8, SU3_ROW2: 3}[_REPS[rep]]
+    return {FUND: 2, FUND_SU2: 2, ADJ: 3, ADJ_SU2: 3, CPLX3: 3, CPLX4: 4, CPLX6: 6, REAL8: 8, SU3_ROW2: 3,
+            CPLX10: 10, REAL15: 15}[_REPS[rep]]
 
 
 def base_rep(rep):
@@ -266,7 +268,7 @@ def pack_gauge(U_nat, dims, rep, prec):
 def unpack_gauge(U, dims, rep, prec):
     rep, prec = _REPS[rep], _PRECS[prec]
     V = Geometry(tuple(dims), rep).volume
-    if rep in (ADJ, REAL8):
+    if rep in (ADJ, REAL8, REAL15):
         n = ncolour(rep)
         out = torch.empty((4, V, n, n), dtype=torch.float64, device=U.device)
     elif rep >= CPLX3:

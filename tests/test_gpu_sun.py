@@ -1,6 +1,7 @@
 """GPU parity for SU(N > 2) with fermions in the fundamental, adjoint and
 two-index representations (Sec. 1), through the dense link formats CPLX3,
-CPLX4, CPLX6 and REAL8.
+CPLX4, CPLX6, CPLX10, REAL8 and REAL15 (SU(3): fundamental, adjoint,
+symmetric, antisymmetric; SU(4): the same four).
 
 * the library's representation of fundamental SU(3) / SU(4) links equals the
   oracle's map entry by entry (same bases) to FP64 rounding; pack/unpack of
@@ -25,7 +26,7 @@ from paper_2411_18511_amd import inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-CASES = [(3, "fund"), (3, "adj"), (3, "sym"), (3, "asym"), (4, "fund"), (4, "asym")]
+CASES = [(3, "fund"), (3, "adj"), (3, "sym"), (3, "asym"), (4, "fund"), (4, "adj"), (4, "sym"), (4, "asym")]
 LATS = [(4, 4, 4, 4), (6, 4, 6, 10), (2, 2, 2, 2), (4, 2, 2, 6)]
 
 
@@ -45,7 +46,7 @@ def test_represent_and_pack(oracle, nc, rep):
     got = h.unpack_gauge(F.U64, dims, F.fmt, "f64").cpu().numpy()
     V = int(np.prod(dims))
     want = F.U_orc.reshape(4, V, F.n, F.n)
-    if F.fmt == h.REAL8:
+    if F.fmt in (h.REAL8, h.REAL15):
         want = want.real
     assert np.abs(got - want).max() < 1e-14
     # natural -> packed -> natural is exact in FP64
@@ -161,7 +162,7 @@ def test_force_sun(oracle, nc, rep):
     h = hrd()
     dims, m0 = (4, 2, 4, 6), -0.3
     F = FieldSUN(dims, nc, rep, seed=41)
-    real = F.fmt == h.REAL8
+    real = F.fmt in (h.REAL8, h.REAL15)
     V = int(np.prod(dims))
 
     def unpack_force(Fp):
@@ -182,7 +183,8 @@ def test_force_sun(oracle, nc, rep):
 def test_sun_errors():
     h = hrd()
     dims = (4, 4, 4, 4)
-    assert h.sun_rep_format(4, "sym") is None and h.sun_rep_format(5, "fund") is None
+    assert h.sun_rep_format(2, "sym") is None and h.sun_rep_format(5, "fund") is None
+    assert h.sun_rep_format(4, "sym") == h.CPLX10 and h.sun_rep_format(4, "adj") == h.REAL15
     F = FieldSUN(dims, 3, "sym", seed=31)
     # the clover and batched paths take the SU(2) formats only
     with pytest.raises(h.HrdError) as e:
@@ -239,7 +241,7 @@ def test_represent_backward_sun(oracle, nc, rep):
     h = hrd()
     dims, m0 = (4, 2, 4, 6), -0.3
     F = FieldSUN(dims, nc, rep, seed=61)
-    real = F.fmt == h.REAL8
+    real = F.fmt in (h.REAL8, h.REAL15)
     V = int(np.prod(dims))
     rng = np.random.default_rng(62)
     shape = (4,) + dims + (F.n, F.n)
@@ -268,7 +270,7 @@ def test_represent_backward_sun_errors():
     F = FieldSUN(dims, 3, "adj", seed=64)
     Uf64 = h.pack_gauge(to_dev_gauge(F.Uf), dims, "cplx3", "f64")
     with pytest.raises(ValueError):
-        h.represent_backward_sun(Uf64, F.U64, dims, 4, "sym")  # no SU(4) symmetric format yet
+        h.represent_backward_sun(Uf64, F.U64, dims, 5, "sym")  # no SU(5) formats
     import ctypes
 
     st = h._lib.hrd_represent_backward_sun(ctypes.byref(h.lattice(dims)), 3, 1, Uf64.data_ptr(), F.U64.data_ptr(),
