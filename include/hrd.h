@@ -608,7 +608,12 @@ size_t hrd_batched_workspace_bytes(const hrd_problem *probs, int nprob, hrd_pari
 /* For every problem and right-hand side k: dst_k = X src_k with X as in
    hrd_dirac_apply (parity HRD_EO, HRD_HOP_EO or HRD_HOP_OE; FP32 packed half
    fields), with one persistent launch per hopping stage covering all
-   problems.  tune may be NULL (defaults).  Asynchronous. */
+   problems.  Formats: the SU(2) formats (HRD_FUND, HRD_ADJ, HRD_FUND_SU2,
+   HRD_ADJ_SU2) in any mix, each site's 8 links held in registers across the
+   right-hand sides of a tile; or problems that all share one dense SU(N > 2)
+   format, whose links are streamed by row for every right-hand side (from
+   L2 after the first); any other mix is HRD_EINVAL.  tune may be NULL
+   (defaults).  Asynchronous. */
 hrd_status hrd_dirac_apply_batched(const hrd_problem *probs, int nprob, hrd_parity parity,
                                    int dagger, const hrd_tune *tune, void *work,
                                    size_t work_bytes, void *stream);

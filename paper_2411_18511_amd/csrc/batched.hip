@@ -23,7 +23,7 @@
 #include <vector>
 
 #include "api_util.h"
-#include "spin.h"
+#include "hop.h"
 
 namespace hrd {
 
@@ -93,6 +93,77 @@ __device__ __forceinline__ void dir_term(const typename LinkIO<REP, float>::Link
     reconstruct<MU, SIG, N, float>(acc, u0, u1);
 }
 
+// Block-wide sum of ||out||^2 for one right-hand side of a tile; every
+// thread of the block reaches it.
+__device__ __forceinline__ void tile_norm_partial(double nrm, double *dst)
+{
+    __shared__ double part[16];
+    for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) t += part[wv];
+        *dst = t;
+    }
+    __syncthreads();
+}
+
+// A tile of a dense SU(N > 2) format: N x N links do not fit in registers,
+// so each right-hand side streams them by row (from L2 after the first
+// right-hand side of the tile) through the single-problem direction terms:
+// the same operations in the same order as the single-problem kernel.
+template <int REP, bool DAG, bool EPI2, bool RUPD>
+__device__ __forceinline__ void batched_tile_dense(const BatchDesc &d, int sb, int r0, int gcount, int w, bool in,
+                                                   int parity, int src_id, int self_id, int dst_id, const int *mode,
+                                                   double *partials, int part_stride, const double *sc)
+{
+    constexpr int NC = 4 * NCol<REP>::value;
+    const Geom &g = d.g;
+    int idx = 0;
+    Site s{};
+    if (in) s = slab_site(g, w, parity, &idx);
+    const float ca = (float)d.m, cb = EPI2 ? (float)(0.5 / d.m) : -0.5f;
+#pragma unroll 1
+    for (int k = 0; k < gcount; k++) {
+        const int rhs = r0 + k;
+        if (mode && mode[d.rhs_base + rhs] == M_DONE) continue;  // uniform
+        double nrm = 0;
+        if (in) {
+            const char *src = d.buf[src_id] + (size_t)rhs * d.fbytes;
+            Cx<float> acc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) acc[c] = Cx<float>{0.f, 0.f};
+            hop_dir_dense<0, DAG, REP, float>(g, s, idx, parity, d.U32, src, acc);
+            hop_dir_dense<1, DAG, REP, float>(g, s, idx, parity, d.U32, src, acc);
+            hop_dir_dense<2, DAG, REP, float>(g, s, idx, parity, d.U32, src, acc);
+            hop_dir_dense<3, DAG, REP, float>(g, s, idx, parity, d.U32, src, acc);
+            Cx<float> out[NC];
+            if constexpr (EPI2) {
+                Cx<float> sv[NC];
+                SpinorIO<float>::template load<NC>(d.buf[self_id] + (size_t)rhs * d.fbytes, g.Vh, idx, sv);
+#pragma unroll
+                for (int c = 0; c < NC; c++) out[c] = axpby(ca, sv[c], cb, acc[c]);
+                if constexpr (RUPD) {
+                    const float alpha = (float)sc[(size_t)(d.rhs_base + rhs) * S_COUNT + S_ALPHA];
+                    Cx<float> rv[NC];
+                    SpinorIO<float>::template load<NC>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, rv);
+#pragma unroll
+                    for (int c = 0; c < NC; c++) out[c] = Cx<float>{rv[c].re - alpha * out[c].re,
+                                                                    rv[c].im - alpha * out[c].im};
+                }
+#pragma unroll
+                for (int c = 0; c < NC; c++) nrm += (double)out[c].re * out[c].re + (double)out[c].im * out[c].im;
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; c++) out[c] = cb * acc[c];
+            }
+            SpinorIO<float>::template store<NC, !RUPD>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, out);
+        }
+        if (EPI2 && partials != nullptr) tile_norm_partial(nrm, &partials[(size_t)(d.rhs_base + rhs) * part_stride + sb]);
+    }
+}
+
 // One tile: sites [sb * blockDim, +blockDim) of the target parity, right-hand
 // sides [grp * G, +G) of the problem.  Each thread loads its site's 8 links
 // once into registers and then applies them to the right-hand sides one
@@ -119,6 +190,11 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
     if (!any) return;  // uniform across the block
     const int w = sb * (int)blockDim.x + (int)threadIdx.x;
     const bool in = w < g.Vh;
+    if constexpr (is_dense(REP)) {
+        batched_tile_dense<REP, DAG, EPI2, RUPD>(d, sb, r0, gcount, w, in, parity, src_id, self_id, dst_id, mode,
+                                                 partials, part_stride, sc);
+        return;
+    }
     int idx = 0;
     int jf[4] = {0, 0, 0, 0}, jb[4] = {0, 0, 0, 0};
     bool nf = false, nb = false;
@@ -176,24 +252,15 @@ __device__ __forceinline__ void batched_tile(const BatchDesc &d, int sb, int grp
             }
             SpinorIO<float>::template store<NC, !RUPD>(d.buf[dst_id] + (size_t)rhs * d.fbytes, g.Vh, idx, out);
         }
-        if (EPI2 && partials != nullptr) {
-            // block-wide sum of ||out||^2, only when the caller wants it (a
-            // uniform kernel argument); every thread of the block reaches it
-            __shared__ double part[16];
-            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nrm;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double t = 0;
-                for (int wv = 0; wv < (int)(blockDim.x >> 6); wv++) t += part[wv];
-                partials[(size_t)(d.rhs_base + rhs) * part_stride + sb] = t;
-            }
-            __syncthreads();
-        }
+        // block-wide sum of ||out||^2, only when the caller wants it (a
+        // uniform kernel argument)
+        if (EPI2 && partials != nullptr) tile_norm_partial(nrm, &partials[(size_t)(d.rhs_base + rhs) * part_stride + sb]);
     }
 }
 
-template <bool DAG, bool EPI2, bool RUPD>
+// GROUP 0: problems in the SU(2) formats, in any mix; otherwise every
+// problem uses the dense SU(N > 2) format GROUP.
+template <bool DAG, bool EPI2, bool RUPD, int GROUP>
 __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs, int nprob, int ntiles, int G,
                                                           int parity, int src_id, int self_id, int dst_id,
                                                           const int *mode, double *partials, int part_stride,
@@ -213,6 +280,11 @@ __global__ __launch_bounds__(256) void batched_hop_kernel(const BatchDesc *descs
         const int local = tile - d.tile_base;
         const int sb = local / d.ngroups;
         const int grp = local - sb * d.ngroups;
+        if constexpr (GROUP != 0) {
+            batched_tile<GROUP, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode, partials,
+                                                 part_stride, sc);
+            continue;
+        }
         switch (d.rep) {
             case HRD_FUND:
                 batched_tile<HRD_FUND, DAG, EPI2, RUPD>(d, sb, grp, G, parity, src_id, self_id, dst_id, mode,
@@ -359,6 +431,10 @@ struct Carve {
     size_t used() const { return (off + 255) & ~(size_t)255; }
 };
 
+// Kernel family of a batch: 0 for the SU(2) formats (mixed freely), else the
+// dense SU(N > 2) format every problem of the batch uses.
+int batch_group(int rep) { return is_dense(rep) ? rep : 0; }
+
 hrd_status check_problems(const hrd_problem *probs, int nprob, bool need_u64)
 {
     if (!probs || nprob < 1 || nprob > kMaxProb) return fail(HRD_EINVAL, "nprob must be in 1..%d", kMaxProb);
@@ -367,7 +443,9 @@ hrd_status check_problems(const hrd_problem *probs, int nprob, bool need_u64)
         const hrd_problem &p = probs[i];
         HRD_TRY(check_lattice(&p.lat));
         HRD_TRY(check_rep_prec(p.rep, HRD_F32));
-        if (is_dense(p.rep)) return fail(HRD_EINVAL, "problem %d: batched launches take the SU(2) link formats", i);
+        if (is_dense(p.rep) ? p.rep != probs[0].rep : is_dense(probs[0].rep))
+            return fail(HRD_EINVAL, "problem %d: a batch takes the SU(2) formats in any mix, or problems of one dense "
+                                    "SU(N) format", i);
         if (p.nrhs < 1 || p.nrhs > kMaxRhs) return fail(HRD_EINVAL, "problem %d: nrhs must be in 1..%d", i, kMaxRhs);
         if (!p.U32 || !p.src || !p.dst) return fail(HRD_EINVAL, "problem %d: NULL pointer", i);
         if (need_u64 && !p.U64) return fail(HRD_EINVAL, "problem %d: the batched CG needs U64", i);
@@ -448,31 +526,44 @@ int build_descs(const hrd_problem *probs, int nprob, const hrd_tune &t, std::vec
 
 template <bool DAG, bool EPI2, bool RUPD>
 hipError_t launch_stage_t(const hrd_tune &t, hipStream_t st, const BatchDesc *dd, int nprob, int ntiles, int parity,
-                          int s, int self, int dst, const int *mode, double *parts, int ps, const double *sc)
+                          int s, int self, int dst, const int *mode, double *parts, int ps, const double *sc,
+                          int group)
 {
     int grid = kNumCu * t.blocks_per_cu;
     grid = (grid / kNumXcd) * kNumXcd;
-    hipLaunchKernelGGL((batched_hop_kernel<DAG, EPI2, RUPD>), dim3(grid), dim3(t.sites_per_tile), 0, st, dd, nprob,
-                       ntiles, t.rhs_per_tile, parity, s, self, dst, mode, parts, ps, sc);
+#define HRD_BATCHED(GRP)                                                                                        \
+    hipLaunchKernelGGL((batched_hop_kernel<DAG, EPI2, RUPD, GRP>), dim3(grid), dim3(t.sites_per_tile), 0, st, dd, \
+                       nprob, ntiles, t.rhs_per_tile, parity, s, self, dst, mode, parts, ps, sc)
+    switch (group) {
+        case 0: HRD_BATCHED(0); break;
+        case HRD_CPLX3: HRD_BATCHED(HRD_CPLX3); break;
+        case HRD_CPLX4: HRD_BATCHED(HRD_CPLX4); break;
+        case HRD_CPLX6: HRD_BATCHED(HRD_CPLX6); break;
+        case HRD_REAL8: HRD_BATCHED(HRD_REAL8); break;
+        case HRD_SU3_ROW2: HRD_BATCHED(HRD_SU3_ROW2); break;
+        case HRD_CPLX10: HRD_BATCHED(HRD_CPLX10); break;
+        default: HRD_BATCHED(HRD_REAL15); break;
+    }
+#undef HRD_BATCHED
     return hipGetLastError();
 }
 
 // One hopping stage over every problem.  sc != NULL (batched CG, with epi2
 // and dagger): the stage updates the residual in buffer dst (r -= alpha Ap).
-hipError_t launch_stage(const hrd_tune &t, bool dag, bool epi2, hipStream_t st, const BatchDesc *dd, int nprob,
-                        int ntiles, int parity, int s, int self, int dst, const int *mode, double *parts, int ps,
-                        const double *sc = nullptr)
+hipError_t launch_stage(int group, const hrd_tune &t, bool dag, bool epi2, hipStream_t st, const BatchDesc *dd,
+                        int nprob, int ntiles, int parity, int s, int self, int dst, const int *mode, double *parts,
+                        int ps, const double *sc = nullptr)
 {
     if (sc) {
         if (!dag || !epi2) return hipErrorInvalidValue;
-        return launch_stage_t<true, true, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+        return launch_stage_t<true, true, true>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc, group);
     }
     if (dag) {
-        if (epi2) return launch_stage_t<true, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
-        return launch_stage_t<true, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+        if (epi2) return launch_stage_t<true, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc, group);
+        return launch_stage_t<true, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc, group);
     }
-    if (epi2) return launch_stage_t<false, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
-    return launch_stage_t<false, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc);
+    if (epi2) return launch_stage_t<false, true, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc, group);
+    return launch_stage_t<false, false, false>(t, st, dd, nprob, ntiles, parity, s, self, dst, mode, parts, ps, sc, group);
 }
 
 // Workspace of the batched apply: descriptor table, then one FP32 odd
@@ -495,15 +586,16 @@ hrd_status run_batched(const std::vector<BatchDesc> &hd, BatchDesc *dd, int ntil
                        hrd_parity parity, bool dag, hipStream_t st)
 {
     const int np = (int)hd.size();
+    const int grp = batch_group(hd[0].rep);
     HRD_TRY(check_hip(hipMemcpyAsync(dd, hd.data(), sizeof(BatchDesc) * np, hipMemcpyHostToDevice, st), "desc upload"));
     hipError_t e;
     if (parity == HRD_EO) {
         // buffers: 0 src, 1 dst, 2 tmp
-        e = launch_stage(t, dag, false, st, dd, np, ntiles, 1, 0, 0, 2, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = launch_stage(t, dag, true, st, dd, np, ntiles, 0, 2, 0, 1, nullptr, nullptr, 0);
+        e = launch_stage(grp, t, dag, false, st, dd, np, ntiles, 1, 0, 0, 2, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = launch_stage(grp, t, dag, true, st, dd, np, ntiles, 0, 2, 0, 1, nullptr, nullptr, 0);
     } else {
         const int target = parity == HRD_HOP_EO ? 0 : 1;
-        e = launch_stage(t, dag, false, st, dd, np, ntiles, target, 0, 0, 1, nullptr, nullptr, 0);
+        e = launch_stage(grp, t, dag, false, st, dd, np, ntiles, target, 0, 0, 1, nullptr, nullptr, 0);
     }
     return check_hip(e, "batched hop launch");
 }
@@ -627,6 +719,7 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
 {
     const auto t_start = std::chrono::steady_clock::now();
     HRD_TRY(check_problems(probs, nprob, true));
+    const int grp = batch_group(probs[0].rep);
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HRD_EINVAL, "tol must be positive");
     if (maxiter < 0) return fail(HRD_EINVAL, "maxiter must be >= 0");
     if (!work) return fail(HRD_EINVAL, "NULL workspace");
@@ -757,13 +850,13 @@ hrd_status hrd_cg_solve_batched(const hrd_problem *probs, int nprob, double tol,
         it++;
         const int P = kBufRing + j;
         // q = D^ p (norm partials), alpha; r -= alpha D^+ q (norm partials)
-        BT(launch_stage(t, false, false, st, w.dd, nprob, ntiles, 1, P, P, B_T, w.mode, nullptr, 0), "hop");
-        BT(launch_stage(t, false, true, st, w.dd, nprob, ntiles, 0, B_T, P, B_Q, w.mode, w.parts, part_stride), "hop");
+        BT(launch_stage(grp, t, false, false, st, w.dd, nprob, ntiles, 1, P, P, B_T, w.mode, nullptr, 0), "hop");
+        BT(launch_stage(grp, t, false, true, st, w.dd, nprob, ntiles, 0, B_T, P, B_Q, w.mode, w.parts, part_stride), "hop");
         hipLaunchKernelGGL(bcg_alpha_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc,
                            w.ahist, j);
         BT(hipGetLastError(), "alpha");
-        BT(launch_stage(t, true, false, st, w.dd, nprob, ntiles, 1, B_Q, B_Q, B_T, w.mode, nullptr, 0), "hop");
-        BT(launch_stage(t, true, true, st, w.dd, nprob, ntiles, 0, B_T, B_Q, B_R, w.mode, w.parts, part_stride, w.sc),
+        BT(launch_stage(grp, t, true, false, st, w.dd, nprob, ntiles, 1, B_Q, B_Q, B_T, w.mode, nullptr, 0), "hop");
+        BT(launch_stage(grp, t, true, true, st, w.dd, nprob, ntiles, 0, B_T, B_Q, B_R, w.mode, w.parts, part_stride, w.sc),
            "hop, r update");
         hipLaunchKernelGGL(bcg_beta_kernel, dim3(total), dim3(256), 0, st, w.rd, w.mode, w.parts, part_stride, w.sc);
         BT(hipGetLastError(), "beta");
