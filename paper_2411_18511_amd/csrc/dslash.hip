@@ -60,9 +60,19 @@ hipError_t hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool norm, b
 
 int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
-hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov)
+// Whether every spinor and link block an FP64 hop of this geometry reads is
+// below 2 GiB, so that 32-bit offsets from the block bases address it.
+bool blocks_fit_32(int rep, const Geom &g)
 {
-    if (is_dense(rep)) return launch_hop_rupdate_dense(rep, prec, a, st, clov);
+    const long long lim = 1ll << 31;
+    return (long long)g.Vh * spinor_site_bytes(rep, HRD_F64) < lim && (long long)g.Vh * link_bytes(rep, HRD_F64) < lim;
+}
+
+hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a0, hipStream_t st, int clov)
+{
+    if (is_dense(rep)) return launch_hop_rupdate_dense(rep, prec, a0, st, clov);
+    HopArgs a = a0;
+    a.rel = prec == HRD_F64 && blocks_fit_32(rep, a.g);
     switch (prec) {
         case HRD_F64: return rupd_for<double>(rep, a, st, clov);
         case HRD_F32: return rupd_for<float>(rep, a, st, clov);
@@ -70,10 +80,12 @@ hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t s
     }
 }
 
-hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
+hipError_t launch_hop(int rep, int prec, const HopArgs &a0, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st, int clov)
 {
-    if (is_dense(rep)) return launch_hop_dense(rep, prec, a, dag, has_a, norm, full, st, clov);
+    if (is_dense(rep)) return launch_hop_dense(rep, prec, a0, dag, has_a, norm, full, st, clov);
+    HopArgs a = a0;
+    a.rel = prec == HRD_F64 && blocks_fit_32(rep, a.g);
     switch (prec) {
         case HRD_F64: return hop_for<double>(rep, a, dag, has_a, norm, full, st, clov);
         case HRD_F32: return hop_for<float>(rep, a, dag, has_a, norm, full, st, clov);

@@ -50,7 +50,8 @@ __device__ __forceinline__ void dir_fence(Cx<R> (&acc)[NC])
 }
 
 // S: storage type of the source spinor and the links; R: arithmetic type.
-template <int MU, bool DAG, int REP, typename S, bool NTL = kNtLinks, typename R = typename Arith<S>::type>
+template <int MU, bool DAG, int REP, typename S, bool NTL = kNtLinks, bool REL = false,
+          typename R = typename Arith<S>::type>
 __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, int p, const void *U,
                                         const char *src, Cx<R> (&acc)[4 * NCol<REP>::value])
 {
@@ -63,8 +64,8 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
     {
         const int j = nbr_fwd(g, s, MU);
         Cx<R> psi[NC];
-        IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::template load<NTL>(U, g.Vh, p, MU, idx);
+        IO::template load<NC, false, REL>(src, g.Vh, j, psi);
+        const auto l = LIO::template load<NTL, REL>(U, g.Vh, p, MU, idx);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SF, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == g.L[0] - 1) {
@@ -81,8 +82,8 @@ __device__ __forceinline__ void hop_dir(const Geom &g, const Site &s, int idx, i
     {
         const int j = nbr_bwd(g, s, MU);
         Cx<R> psi[NC];
-        IO::template load<NC>(src, g.Vh, j, psi);
-        const auto l = LIO::template load<NTL>(U, g.Vh, 1 - p, MU, j);
+        IO::template load<NC, false, REL>(src, g.Vh, j, psi);
+        const auto l = LIO::template load<NTL, REL>(U, g.Vh, 1 - p, MU, j);
         Cx<R> h0[N], h1[N], u0[N], u1[N];
         project<MU, SB, N, R>(psi, h0, h1);
         if (MU == 0 && s.x[0] == 0) {
@@ -257,8 +258,8 @@ __device__ __forceinline__ void hop_dir_dense(const Geom &g, const Site &s, int 
 // S is the storage type of the operator's spinors and links (double, float or
 // h16), R = Arith<S>::type the arithmetic; the residual of the RUPD epilogue
 // and the clover fields are stored in R.
-template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE>
-__global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
+template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD, int CLOV, bool REL>
+__device__ __forceinline__ void hop_body(const HopArgs &a)
 {
     using R = typename Arith<S>::type;
     constexpr int N = NCol<REP>::value;
@@ -297,10 +298,10 @@ __global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
             hop_dir_dense<3, DAG, REP, S>(g, s, idx, p, a.U, src, acc);
         } else {
             constexpr bool NTL = FULL ? kNtLinksFull : kNtLinks;
-            hop_dir<0, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            hop_dir<1, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            hop_dir<2, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
-            hop_dir<3, DAG, REP, S, NTL>(g, s, idx, p, a.U, src, acc);
+            hop_dir<0, DAG, REP, S, NTL, REL>(g, s, idx, p, a.U, src, acc);
+            hop_dir<1, DAG, REP, S, NTL, REL>(g, s, idx, p, a.U, src, acc);
+            hop_dir<2, DAG, REP, S, NTL, REL>(g, s, idx, p, a.U, src, acc);
+            hop_dir<3, DAG, REP, S, NTL, REL>(g, s, idx, p, a.U, src, acc);
         }
         const R cb = (R)a.b;
         Cx<R> out[NC];
@@ -352,13 +353,37 @@ __global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
     }
 }
 
+template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE,
+          bool REL = false>
+__global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
+{
+    hop_body<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, REL>(a);
+}
+
+// FP64 SU(2) formats take the kernel with 32-bit-offset loads when the host
+// has found every block below 2 GiB (HopArgs::rel), else 64-bit addresses.
+// A single kernel holding both paths behind a uniform branch measured slower
+// than either.
+template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD, int CLOV>
+void launch_hop_kernel(const HopArgs &a, dim3 grid, hipStream_t st)
+{
+    if constexpr (std::is_same<S, double>::value && !is_dense(REP)) {
+        if (a.rel) {
+            hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, true>), grid, dim3(kHopBlock), 0,
+                               st, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, false>), grid, dim3(kHopBlock), 0, st,
+                       a);
+}
+
 template <int REP, typename S, int CLOV>
 hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
 {
     const int nb = hop_blocks(a.g) * (full ? 2 : 1);
-    const dim3 grid(nb), block(kHopBlock);
-#define HRD_LAUNCH(D, A, NR, F) \
-    hipLaunchKernelGGL((hop_kernel<REP, S, D, A, NR, F, false, CLOV>), grid, block, 0, st, a)
+    const dim3 grid(nb);
+#define HRD_LAUNCH(D, A, NR, F) launch_hop_kernel<REP, S, D, A, NR, F, false, CLOV>(a, grid, st)
     if constexpr (CLOV == CLOV_INV) {
         // M^{-1} (b H src): no self term, no norm
         if (dag) HRD_LAUNCH(true, false, false, false);
@@ -415,13 +440,11 @@ hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st, int clov)
 {
     if constexpr (clover_capable(REP)) {
         if (clov == CLOV_SELF) {
-            hipLaunchKernelGGL((hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>), dim3(hop_blocks(a.g)),
-                               dim3(kHopBlock), 0, st, a);
+            launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>(a, dim3(hop_blocks(a.g)), st);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((hop_kernel<REP, S, true, true, true, false, true>), dim3(hop_blocks(a.g)), dim3(kHopBlock), 0,
-                       st, a);
+    launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_NONE>(a, dim3(hop_blocks(a.g)), st);
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ struct HopArgs {
     void *r;            // RUPD: residual updated in place, r <- r - alpha * out
     const double *sc;   // RUPD: device scalars (alpha in slot S_ALPHA)
     const void *clov;   // clover epilogues: packed site matrices of the target parity's field
+    int rel;            // FP64 SU(2) formats: every spinor and link block is below 2 GiB, so
+                        // loads address it with 32-bit offsets (set by launch_hop)
 };
 
 // Clover epilogues of the hopping kernel (the site matrix M = m + A is read

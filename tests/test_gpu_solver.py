@@ -229,7 +229,7 @@ def test_abi_error_paths():
     assert lib.hrd_dirac_apply(ctypes.byref(bad), 0, 0, 1, 1, 2, 0.0, 0, 0, None, None) == h.ESHAPE
     assert "even" in lib.hrd_last_error().decode()
     lat = h.lattice((4, 4, 4, 4))
-    assert lib.hrd_dirac_apply(ctypes.byref(lat), 9, 0, 1, 1, 2, 0.0, 0, 0, None, None) == h.EINVAL
+    assert lib.hrd_dirac_apply(ctypes.byref(lat), 11, 0, 1, 1, 2, 0.0, 0, 0, None, None) == h.EINVAL
     assert lib.hrd_dirac_apply(ctypes.byref(lat), 0, 0, None, 1, 2, 0.0, 0, 0, None, None) == h.EINVAL
     dims = (4, 4, 4, 4)
     F = Field(dims, "fund", seed=51)
