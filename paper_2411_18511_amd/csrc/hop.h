@@ -34,6 +34,18 @@ constexpr bool kNtStore = true;
 
 constexpr int kHopBlock = 256;  // threads per workgroup of the hopping kernel
 
+// Workgroup size of one instantiation.  The FP64 kernels of the SU(2) formats
+// hold one wave per SIMD; without a norm partial they run one-wave workgroups,
+// so each SIMD starts its next workgroup as soon as its own wave ends instead
+// of waiting for the slowest of four (48^4 FP64 hop 394 -> 381 us, plain D
+// 739 -> 716 us).  Kernels that emit a ||out||^2 partial keep kHopBlock sites
+// per partial, the granularity the CG reductions expect.
+template <int REP, typename S, bool NORM, bool RUPD>
+constexpr int hop_block()
+{
+    return (std::is_same<S, double>::value && !is_dense(REP) && !NORM && !RUPD) ? 64 : kHopBlock;
+}
+
 namespace {
 
 // Barrier between the direction terms of the dense formats: the accumulator
@@ -283,7 +295,7 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
         self = a.self;
         dst = a.dst;
     }
-    const int w = lb * kHopBlock + threadIdx.x;
+    const int w = lb * hop_block<REP, S, NORM, RUPD>() + threadIdx.x;
     double nrm = 0;
     if (w < g.Vh) {
         int idx;
@@ -355,7 +367,7 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
 
 template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE,
           bool REL = false>
-__global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__((hop_block<REP, S, NORM, RUPD>())) void hop_kernel(HopArgs a)
 {
     hop_body<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, REL>(a);
 }
@@ -365,25 +377,24 @@ __global__ __launch_bounds__(kHopBlock) void hop_kernel(HopArgs a)
 // A single kernel holding both paths behind a uniform branch measured slower
 // than either.
 template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD, int CLOV>
-void launch_hop_kernel(const HopArgs &a, dim3 grid, hipStream_t st)
+void launch_hop_kernel(const HopArgs &a, hipStream_t st)
 {
+    constexpr int blk = hop_block<REP, S, NORM, RUPD>();
+    const dim3 grid(((a.g.Vh + blk - 1) / blk) * (FULL ? 2 : 1));
     if constexpr (std::is_same<S, double>::value && !is_dense(REP)) {
         if (a.rel) {
-            hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, true>), grid, dim3(kHopBlock), 0,
-                               st, a);
+            hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, true>), grid, dim3(blk), 0, st,
+                               a);
             return;
         }
     }
-    hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, false>), grid, dim3(kHopBlock), 0, st,
-                       a);
+    hipLaunchKernelGGL((hop_kernel<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, false>), grid, dim3(blk), 0, st, a);
 }
 
 template <int REP, typename S, int CLOV>
 hipError_t dispatch_hop(const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st)
 {
-    const int nb = hop_blocks(a.g) * (full ? 2 : 1);
-    const dim3 grid(nb);
-#define HRD_LAUNCH(D, A, NR, F) launch_hop_kernel<REP, S, D, A, NR, F, false, CLOV>(a, grid, st)
+#define HRD_LAUNCH(D, A, NR, F) launch_hop_kernel<REP, S, D, A, NR, F, false, CLOV>(a, st)
     if constexpr (CLOV == CLOV_INV) {
         // M^{-1} (b H src): no self term, no norm
         if (dag) HRD_LAUNCH(true, false, false, false);
@@ -440,11 +451,11 @@ hipError_t dispatch_rupd(const HopArgs &a, hipStream_t st, int clov)
 {
     if constexpr (clover_capable(REP)) {
         if (clov == CLOV_SELF) {
-            launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>(a, dim3(hop_blocks(a.g)), st);
+            launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_SELF>(a, st);
             return hipGetLastError();
         }
     }
-    launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_NONE>(a, dim3(hop_blocks(a.g)), st);
+    launch_hop_kernel<REP, S, true, true, true, false, true, CLOV_NONE>(a, st);
     return hipGetLastError();
 }
 
