@@ -20,7 +20,8 @@ One step = one pass over every stage of the hot path:
      FP32, and CG on D^_sw^+ D^_sw in FP64 and mixed precision (FP32 and F16);
 for full and first-row link storage.  After the steps, once each: the
 bandwidth ceiling (stream probes), the adjoint representation at 48^4, the
-mixed-volume batched CG, the adjoint and SU(3) stages at 32^4, and the CPU
+mixed-volume batched CG, the adjoint and SU(3) stages at 32^4, the SU(4)
+stage at 24^4, and the CPU
 oracle (timings and the error of each GPU solution against the oracle's
 FP64 solution).
 
@@ -501,25 +502,33 @@ def adjoint_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1
     return out
 
 
-SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx6": 36 * 16, "real8": 64 * 8, "su3_row2": 6 * 16}  # FP64, unpadded
+SUN_LINK_BYTES = {"cplx3": 9 * 16, "cplx4": 16 * 16, "cplx6": 36 * 16, "cplx10": 100 * 16, "real8": 64 * 8,
+                  "real15": 225 * 8, "su3_row2": 6 * 16}  # FP64, unpadded
+SUN_FORMAT_NAMES = {"cplx3": "CPLX3", "cplx4": "CPLX4", "cplx6": "CPLX6", "cplx10": "CPLX10", "real8": "REAL8",
+                    "real15": "REAL15"}
 
 
-def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10, m0=-0.3):
-    """SU(3) with fermions in the fundamental (CPLX3), 2-index symmetric (CPLX6)
-    and adjoint (REAL8) representations: representation build, hopping block
-    in FP64 / FP32 / F16 and even/odd D^ in FP32 (algorithmic bytes on
-    unpadded links), and mixed / MIXED16 CG to 1e-10 for the fundamental; the
-    fundamental also in the two-row format, with the clover-improved D^ (FP32)
-    and MIXED16 clover CG."""
+def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10, m0=-0.3, nc=3):
+    """SU(nc) fermions in the fundamental and higher representations: the
+    representation build, hopping block in FP64 / FP32 / F16 and even/odd D^
+    in FP32 (algorithmic bytes on unpadded links) for every representation.
+    SU(3) (fundamental CPLX3, 2-index symmetric CPLX6, adjoint REAL8): mixed /
+    MIXED16 / FP64 CG to 1e-10 for the fundamental, which also runs in the
+    two-row format with the clover-improved D^ (FP32) and MIXED16 clover CG.
+    SU(4) (fundamental CPLX4, antisymmetric CPLX6, symmetric CPLX10, adjoint
+    REAL15): MIXED16 CG to 1e-10 for every representation, FP64 CG for the
+    fundamental."""
     V = int(np.prod(dims))
-    Uf = inputs.gauge_field_sun(dims, 7, 3, kind="product")
-    Uf_dev = torch.from_numpy(Uf.reshape(4, V, 3, 3)).to(dev)
+    Uf = inputs.gauge_field_sun(dims, 7, nc, kind="product")
+    Uf_dev = torch.from_numpy(Uf.reshape(4, V, nc, nc)).to(dev)
     del Uf
-    Uf64 = hrd.pack_gauge(Uf_dev, dims, "cplx3", "f64")
+    ffmt = "cplx3" if nc == 3 else "cplx4"
+    Uf64 = hrd.pack_gauge(Uf_dev, dims, ffmt, "f64")
     del Uf_dev
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    out = {"dims": list(dims), "group": "SU(3)", "links": "products of embedded Haar SU(2) elements"}
-    for rep in ("fund", "sym", "adj", "fund_row2"):
+    out = {"dims": list(dims), "group": f"SU({nc})", "links": "products of embedded Haar SU(2) elements"}
+    reps_list = ("fund", "sym", "adj", "fund_row2") if nc == 3 else ("fund", "asym", "sym", "adj")
+    for rep in reps_list:
         a, b = ev(), ev()
         if rep == "fund_row2":
             # the same SU(3) links stored as two rows (third row rebuilt in the kernel)
@@ -528,10 +537,10 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
             U64 = hrd.pack_gauge(hrd.unpack_gauge(Uf64, dims, "cplx3", "f64"), dims, fmt, "f64")
             b.record()
         else:
-            fmt = hrd.sun_rep_format(3, rep)
-            name = {hrd.CPLX3: "cplx3", hrd.CPLX6: "cplx6", hrd.REAL8: "real8"}[fmt]
+            fmt = hrd.sun_rep_format(nc, rep)
+            name = next(k for k, v in SUN_FORMAT_NAMES.items() if getattr(hrd, v) == fmt)
             a.record()
-            U64 = hrd.represent_sun(Uf64, dims, 3, rep)
+            U64 = hrd.represent_sun(Uf64, dims, nc, rep)
             b.record()
         n = hrd.ncolour(fmt)
         b.synchronize()
@@ -570,7 +579,7 @@ def sun_stage(torch, hrd, inputs, dev, dims=(32, 32, 32, 32), reps=20, tol=1e-10
                 alg = V * 8 * L + (V // 2) * 5 * S
                 r["dhat_f32"] = {"ms": ms, "alg_GBs": alg / (ms * 1e-3) / 1e9,
                                  "pct_hbm_peak": 100.0 * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-            if rep in ("fund", "fund_row2") and prec != "f64":
+            if (rep in ("fund", "fund_row2") and prec != "f64") or (nc == 4 and prec == "f16"):
                 mode = "mixed" if prec == "f32" else "mixed16"
                 a.record()
                 _, info = hrd.cg_solve(U64, src_e, m0, tol, dims, fmt, mode=mode, U32=Ug)
@@ -882,6 +891,8 @@ def run(args):
         out["adjoint"] = adjoint_stage(torch, hrd, inputs, dev)
         print("[bench] SU(3) representations stage", file=sys.stderr, flush=True)
         out["sun"] = sun_stage(torch, hrd, inputs, dev)
+        print("[bench] SU(4) representations stage", file=sys.stderr, flush=True)
+        out["sun4"] = sun_stage(torch, hrd, inputs, dev, dims=(24, 24, 24, 24), nc=4)
     if args.manifest:
         with open(args.manifest, "w") as f:
             json.dump({"dims": list(dims), "library": hrd.version(), "source_hash": hrd.build_hash(),

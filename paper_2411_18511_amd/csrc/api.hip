@@ -288,7 +288,7 @@ size_t carve_cg(const hrd_lattice *lat, int rep, int mode, void *work, CgBuffers
     const size_t h64 = spinor_bytes(lat, rep, HRD_F64, 1);
     const size_t h32 = spinor_bytes(lat, rep, HRD_F32, 1);
     const Geom g = make_geom(lat->dims);
-    const int nparts = std::max(hop_blocks(g), kRedBlocks) * 2;
+    const int nparts = std::max(hop_partials(rep, HRD_F64, g), kRedBlocks) * 2;
     CgBuffers t{};
     t.r64 = c.take(h64);
     t.q64 = c.take(h64);
@@ -793,7 +793,8 @@ static hrd_status cg_run(const hrd_lattice *lat, hrd_rep rep, hrd_cg_mode mode, 
     const hipStream_t st = (hipStream_t)stream;
     const int nc = ncomp_of(rep);
     const size_t n64 = h64 / 16;
-    const int hb = hop_blocks(g);
+    // ||.||^2 partials written by one operator stage of the iteration
+    const int hb = hop_partials(rep, mode == HRD_CG_F64 ? HRD_F64 : mode == HRD_CG_MIXED16 ? HRD_F16 : HRD_F32, g);
     double sc[S_COUNT];
 
 #define CG_HIP(expr, what)                                        \

@@ -60,6 +60,12 @@ hipError_t hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool norm, b
 
 int hop_blocks(const Geom &g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
+int hop_partials(int rep, int prec, const Geom &g)
+{
+    const int sites = hop_sites_per_block(rep, prec);
+    return (g.Vh + sites - 1) / sites;
+}
+
 // Whether every spinor and link block an FP64 hop of this geometry reads is
 // below 2 GiB, so that 32-bit offsets from the block bases address it.
 bool blocks_fit_32(int rep, const Geom &g)

@@ -22,8 +22,8 @@
 
 namespace hrd {
 
-// Launch shape and cache policy of the hopping kernel (measured on MI355X):
-// 256-thread workgroups; links and outputs are used once per hop and go
+// Cache policy of the hopping kernel (measured on MI355X; the workgroup size
+// is hop_block below): links and outputs are used once per hop and go
 // through non-temporal loads and stores, except in the one-launch plain
 // operator, where every link serves one even and one odd target and the
 // blocks of the two parities at the same position run side by side on one
@@ -32,19 +32,19 @@ constexpr bool kNtLinks = true;
 constexpr bool kNtLinksFull = false;
 constexpr bool kNtStore = true;
 
-constexpr int kHopBlock = 256;  // threads per workgroup of the hopping kernel
+constexpr int kHopBlock = 256;  // threads per workgroup, and sites per norm partial
 
-// Workgroup size of one instantiation.  The FP64 kernels of the SU(2) formats
-// hold one wave per SIMD; without a norm partial they run one-wave workgroups,
-// so each SIMD starts its next workgroup as soon as its own wave ends instead
-// of waiting for the slowest of four (48^4 FP64 hop 394 -> 381 us, plain D
-// 739 -> 716 us).  Kernels that emit a ||out||^2 partial keep kHopBlock sites
-// per partial, the granularity the CG reductions expect.
-template <int REP, typename S, bool NORM, bool RUPD>
+// Workgroup size of one instantiation (hop_sites_per_block).  The FP64
+// kernels of the SU(2) formats hold one wave per SIMD and run one-wave
+// workgroups, so each SIMD starts its next workgroup as soon as its own wave
+// ends instead of waiting for the slowest of four (48^4 FP64 hop
+// 394 -> 381 us, plain D 739 -> 716 us); norm partials follow the workgroups.
+template <int REP, typename S>
 constexpr int hop_block()
 {
-    return (std::is_same<S, double>::value && !is_dense(REP) && !NORM && !RUPD) ? 64 : kHopBlock;
+    return hop_sites_per_block(REP, std::is_same<S, double>::value ? HRD_F64 : HRD_F32);
 }
+static_assert(hop_sites_per_block(HRD_FUND, HRD_F32) == kHopBlock, "hop workgroup sizes");
 
 namespace {
 
@@ -295,7 +295,7 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
         self = a.self;
         dst = a.dst;
     }
-    const int w = lb * hop_block<REP, S, NORM, RUPD>() + threadIdx.x;
+    const int w = lb * hop_block<REP, S>() + threadIdx.x;
     double nrm = 0;
     if (w < g.Vh) {
         int idx;
@@ -360,14 +360,14 @@ __device__ __forceinline__ void hop_body(const HopArgs &a)
         }
     }
     if constexpr (NORM) {
-        const double t = block_sum<kHopBlock>(nrm);
+        const double t = block_sum<hop_block<REP, S>()>(nrm);
         if (threadIdx.x == 0) a.partials[part_idx] = t;
     }
 }
 
 template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD = false, int CLOV = CLOV_NONE,
           bool REL = false>
-__global__ __launch_bounds__((hop_block<REP, S, NORM, RUPD>())) void hop_kernel(HopArgs a)
+__global__ __launch_bounds__((hop_block<REP, S>())) void hop_kernel(HopArgs a)
 {
     hop_body<REP, S, DAG, HAS_A, NORM, FULL, RUPD, CLOV, REL>(a);
 }
@@ -379,7 +379,7 @@ __global__ __launch_bounds__((hop_block<REP, S, NORM, RUPD>())) void hop_kernel(
 template <int REP, typename S, bool DAG, bool HAS_A, bool NORM, bool FULL, bool RUPD, int CLOV>
 void launch_hop_kernel(const HopArgs &a, hipStream_t st)
 {
-    constexpr int blk = hop_block<REP, S, NORM, RUPD>();
+    constexpr int blk = hop_block<REP, S>();
     const dim3 grid(((a.g.Vh + blk - 1) / blk) * (FULL ? 2 : 1));
     if constexpr (std::is_same<S, double>::value && !is_dense(REP)) {
         if (a.rel) {

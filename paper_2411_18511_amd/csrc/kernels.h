@@ -31,11 +31,17 @@ struct HopArgs {
 enum CloverMode { CLOV_NONE = 0, CLOV_SELF = 1, CLOV_INV = 2 };
 
 int hop_blocks(const Geom &g);
+// Sites per workgroup of the hopping kernels of one format and precision:
+// the FP64 kernels of the SU(2) formats run one-wave workgroups (64 sites),
+// every other kernel 256.  A launch that writes ||out||^2 partials writes one
+// per workgroup, hop_partials(rep, prec, g) = ceil(Vh / sites) of them.
+constexpr int hop_sites_per_block(int rep, int prec) { return (prec == HRD_F64 && !is_dense(rep)) ? 64 : 256; }
+int hop_partials(int rep, int prec, const Geom &g);
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st, int clov = CLOV_NONE);
 // Second stage of D^+ fused with the CG residual update: out = a self + b H src
 // is not stored; instead r <- r - alpha out and ||r||^2 partials are written
-// (one per block, hop_blocks(g) of them).
+// (one per workgroup, hop_partials(rep, prec, g) of them).
 hipError_t launch_hop_rupdate(int rep, int prec, const HopArgs &a, hipStream_t st, int clov = CLOV_NONE);
 // the same for the dense SU(N > 2) formats (clover only for CPLX3 and
 // SU3_ROW2), dslash_sun.hip
