@@ -1,9 +1,12 @@
 // Wilson hopping stencil for the dense SU(N > 2) link formats (CPLX3, CPLX4,
-// CPLX6, REAL8, SU3_ROW2): the same kernel template as the SU(2) formats with
-// N x N colour products; clover epilogues for the SU(3) fundamental formats.
+// CPLX6, CPLX10, REAL8, REAL15, SU3_ROW2): the same kernel template as the
+// SU(2) formats with N x N colour products; clover epilogues for the SU(3)
+// fundamental formats.
+#include "hop_lanes.h"
 #include "hop_quad.h"
 
-// REAL8 links in FP64 run on the four-lanes-per-site kernel of hop_quad.h
+// REAL8 links in FP64 run on the four-lanes-per-site kernel of hop_quad.h,
+// CPLX10 links in FP64 on that of hop_lanes.h
 namespace hrd {
 
 namespace {
@@ -12,8 +15,10 @@ template <typename S>
 hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool norm, bool full, hipStream_t st,
                          int clov)
 {
-    if constexpr (std::is_same<S, double>::value)
+    if constexpr (std::is_same<S, double>::value) {
         if (quad_covers(rep, full, a.g.Vh)) return launch_hop_quad(a, dag, has_a, norm, st);
+        if (lanes_covers(rep, full, a.g.Vh)) return launch_hop_lanes<HRD_CPLX10>(a, dag, has_a, norm, st);
+    }
     switch (rep) {
         case HRD_CPLX3: return dispatch_hop_clov<HRD_CPLX3, S>(a, dag, has_a, norm, full, st, clov);
         case HRD_CPLX4: return dispatch_hop<HRD_CPLX4, S, CLOV_NONE>(a, dag, has_a, norm, full, st);
@@ -28,8 +33,10 @@ hipError_t dense_hop_for(int rep, const HopArgs &a, bool dag, bool has_a, bool n
 template <typename S>
 hipError_t dense_rupd_for(int rep, const HopArgs &a, hipStream_t st, int clov)
 {
-    if constexpr (std::is_same<S, double>::value)
+    if constexpr (std::is_same<S, double>::value) {
         if (quad_covers(rep, false, a.g.Vh)) return launch_hop_quad_rupdate(a, st);
+        if (lanes_covers(rep, false, a.g.Vh)) return launch_hop_lanes_rupdate<HRD_CPLX10>(a, st);
+    }
     switch (rep) {
         case HRD_CPLX3: return dispatch_rupd<HRD_CPLX3, S>(a, st, clov);
         case HRD_CPLX4: return dispatch_rupd<HRD_CPLX4, S>(a, st, CLOV_NONE);

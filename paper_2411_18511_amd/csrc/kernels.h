@@ -32,10 +32,14 @@ enum CloverMode { CLOV_NONE = 0, CLOV_SELF = 1, CLOV_INV = 2 };
 
 int hop_blocks(const Geom &g);
 // Sites per workgroup of the hopping kernels of one format and precision:
-// the FP64 kernels of the SU(2) formats run one-wave workgroups (64 sites),
-// every other kernel 256.  A launch that writes ||out||^2 partials writes one
-// per workgroup, hop_partials(rep, prec, g) = ceil(Vh / sites) of them.
-constexpr int hop_sites_per_block(int rep, int prec) { return (prec == HRD_F64 && !is_dense(rep)) ? 64 : 256; }
+// 64 for the FP64 kernels of the SU(2) formats (one-wave workgroups) and of
+// CPLX10 (four lanes per site), 256 for every other kernel.  A launch that
+// writes ||out||^2 partials writes one per workgroup,
+// hop_partials(rep, prec, g) = ceil(Vh / sites) of them.
+constexpr int hop_sites_per_block(int rep, int prec)
+{
+    return (prec == HRD_F64 && (!is_dense(rep) || rep == HRD_CPLX10)) ? 64 : 256;
+}
 int hop_partials(int rep, int prec, const Geom &g);
 hipError_t launch_hop(int rep, int prec, const HopArgs &a, bool dag, bool has_a, bool norm, bool full,
                       hipStream_t st, int clov = CLOV_NONE);

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import FieldSUN, requires_gpu, rel_err, hrd, to_dev_gauge
+from gpu_util import FieldSUN, requires_gpu, rel_err, hrd, site_rel_err, to_dev_gauge
 from paper_2411_18511_amd import inputs
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
@@ -152,6 +152,36 @@ def test_adjoint_su3_f64_many_blocks(oracle):
             out = h.dirac_apply(F.U64, F.pack(x, "f64", sites), m0, F.fmt, par, dims, prec="f64", dagger=dagger)
             err = rel_err(F.unpack(out, "f64", osites), want)
             assert err <= 1e-13, (par, dagger, err)
+    x, info = h.cg_solve(F.U64, F.pack(pe, "f64", "even"), m0, 1e-10, dims, F.fmt, mode="f64")
+    assert info["status"] == "HRD_OK"
+    assert oracle.true_residual(U, pe, F.unpack(x, "f64", "even"), m0) <= 1e-10
+
+
+@pytest.mark.parametrize("rep", ["sym", "adj"])
+def test_su4_f64_many_blocks(oracle, rep):
+    """SU(4) symmetric (CPLX10) and adjoint (REAL15) FP64 operator on
+    8x6x6x10 (1440 sites per parity: 22.5 workgroups of 64 sites of the
+    four-lanes-per-site kernel, a ragged last one): hop blocks, D^ and their
+    daggers against the oracle, and the FP64 CG (fused residual update and
+    one norm partial per 64 sites) to a true residual of 1e-10."""
+    h = hrd()
+    dims, m0 = (8, 6, 6, 10), -0.3
+    F = FieldSUN(dims, 4, rep, seed=33, kind="smeared")
+    U = F.U_orc
+    psi = F.spinor(34)
+    pe, po = oracle.restrict(psi, 0), oracle.restrict(psi, 1)
+    for dagger in (False, True):
+        hb = oracle.hop_block_dagger if dagger else oracle.hop_block
+        dh = oracle.dhat_dagger if dagger else oracle.dhat
+        for par, x, sites, osites, want in (
+                ("hop_eo", po, "odd", "even", oracle.restrict(hb(U, po, 0), 0)),
+                ("hop_oe", pe, "even", "odd", oracle.restrict(hb(U, pe, 1), 1)),
+                ("eo", pe, "even", "even", dh(U, pe, m0))):
+            out = h.dirac_apply(F.U64, F.pack(x, "f64", sites), m0, F.fmt, par, dims, prec="f64", dagger=dagger)
+            got = F.unpack(out, "f64", osites)
+            err = rel_err(got, want)
+            assert err <= 1e-13, (par, dagger, err)
+            assert site_rel_err(got, want) <= 1e-12, (par, dagger)
     x, info = h.cg_solve(F.U64, F.pack(pe, "f64", "even"), m0, 1e-10, dims, F.fmt, mode="f64")
     assert info["status"] == "HRD_OK"
     assert oracle.true_residual(U, pe, F.unpack(x, "f64", "even"), m0) <= 1e-10
